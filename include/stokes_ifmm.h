@@ -1,0 +1,220 @@
+/*
+ * stokes_ifmm.h - C ABI of the MI355X library for the completed double-layer
+ * Stokes boundary-integral system of a pipe filled with circular pores, its
+ * block-diagonal and inverse-FMM preconditioners, and flexible GMRES.
+ *
+ * The problem (Coulier, Quaife, Darve, "An efficient preconditioner for the
+ * fast simulation of a 2D Stokes flow in porous media", Section 2): find the
+ * density sigma on the wall Gamma_0 and the pore boundaries Gamma_k such that
+ * the Nystrom-discretised boundary-integral operator A maps sigma to the
+ * prescribed boundary velocity f (equation "f = A sigma", Section 2.2).  The
+ * operator used here is the double layer of Section 2.1 with its null space
+ * removed: a Stokeslet and a rotlet at every pore centre, with three
+ * constraint rows per pore, and a rank-one flux term on the wall.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers are DEVICE pointers unless marked (host).  All floating
+ *   point is IEEE FP64 unless stated.  The caller allocates and owns every
+ *   array it passes; the library never frees caller memory.  Opaque handles
+ *   are allocated by the library and released by the matching *_destroy.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is stream-ordered.  Entry points that return numbers to the host
+ *   (gmres_solve) synchronise that stream before returning.
+ * - Return value: 0 = OK; 1 = SBIE_NOT_CONVERGED (a warning: outputs hold
+ *   the best iterate); negative = error, with a message available from
+ *   sbie_last_error() on the calling thread.  No C++ exception crosses the
+ *   ABI.
+ *
+ * Unknown vector layout (length n = 2*Nn + 3*M):
+ *   [ sigma_x[0..Nn) | sigma_y[0..Nn) | (lambda_x, lambda_y, mu)_k, k=0..M-1 ]
+ * Node order: pores 0..M-1 (consecutive nodes each), then the wall.
+ *
+ * The operator, row by row (r = x_i - x_j, rho = |r|, t_i = (-ny_i, nx_i)):
+ *   node rows:  -1/2 sigma_i
+ *               + sum_{j != i} w_j (1/pi) (r.n_j) r r^T / rho^4 sigma_j
+ *               + w_i kappa_i / (2 pi) t_i t_i^T sigma_i
+ *               + [i on wall] n_i / |Gamma_0| sum_{j on wall} w_j n_j.sigma_j
+ *               + sum_k [ S(x_i - c_k) lambda_k + r_k R(x_i - c_k) mu_k ]
+ *     with S(q) = (-log|q| I + q q^T/|q|^2)/(4 pi)   (Stokeslet)
+ *          R(q) = (q_y, -q_x)/(4 pi |q|^2)            (rotlet)
+ *   pore rows:  lambda_k row: sum_{j in k} w_j sigma_j / (2 pi r_k) - lambda_k
+ *               mu_k row:     sum_{j in k} w_j (x_j - c_k)_perp . sigma_j
+ *                                        / (2 pi r_k^2) - mu_k
+ */
+#ifndef STOKES_IFMM_H
+#define STOKES_IFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  SBIE_OK = 0,
+  SBIE_NOT_CONVERGED = 1,
+  SBIE_INVALID_ARGUMENT = -1,
+  SBIE_INVALID_GEOMETRY = -2,
+  SBIE_OUT_OF_MEMORY = -3,
+  SBIE_HIP_ERROR = -4,
+  SBIE_BREAKDOWN = -5,
+  SBIE_UNSUPPORTED = -6
+};
+
+/* Discretised boundary (Section 2.2: nodes are the quadrature points of the
+ * trapezoid rule on every closed curve).
+ *   n_nodes      Nn = sum of nodes over the pores and the wall.
+ *   n_pores      M (may be 0).
+ *   curve_off    (host) M+2 offsets; nodes of pore k are
+ *                [curve_off[k], curve_off[k+1]); the wall is curve M.
+ *   curve_off_dev  the same M+2 offsets in device memory.
+ *   x, y         node positions.
+ *   nx, ny       unit normal pointing OUT of the fluid (away from the pipe
+ *                interior on the wall, towards the centre on a pore).
+ *   w            trapezoid weight |x'(t)| 2 pi / N_curve (arclength weight).
+ *   kappa        curvature vector dotted with n: +1/r on a pore, minus the
+ *                curvature on the convex wall.
+ *   cx, cy       pore centres (where the Stokeslet and rotlet sit), length M.
+ *   radius       pore radii, length M.
+ * All device arrays are FP64 and are only read. */
+typedef struct {
+  int64_t n_nodes;
+  int32_t n_pores;
+  int32_t reserved;
+  const int64_t *curve_off;
+  const int64_t *curve_off_dev;
+  const double *x, *y;
+  const double *nx, *ny;
+  const double *w;
+  const double *kappa;
+  const double *cx, *cy;
+  const double *radius;
+} sbie_geom;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *sbie_last_error(void);
+
+/* Entries A[rows, cols] of the operator above (Section 2.2, equation
+ * "f = A sigma"), for arbitrary global row and column indices.
+ *   rows   device int64[nr], each in [0, n).
+ *   cols   device int64[nc], each in [0, n).
+ *   out    device FP64, column-major nr x nc with leading dimension ld >= nr.
+ * Errors: SBIE_INVALID_ARGUMENT for null pointers, nr/nc < 0 or ld < nr.
+ * Indices are not range-checked on the device: out-of-range indices are the
+ * caller's error (undefined result, never an out-of-bounds write to out). */
+int stokes_bie_assemble(const sbie_geom *g, const int64_t *rows, int64_t nr,
+                        const int64_t *cols, int64_t nc, double *out,
+                        int64_t ld, void *stream);
+
+/* y = A x (mode SBIE_MV_FULL), or only the principal-value double-layer sum
+ * with its smooth diagonal limit, sum_{j != i} w_j D(x_i, x_j, n_j) sigma_j
+ * + w_i kappa_i/(2 pi) t t^T sigma_i, in the node rows and zero in the pore
+ * rows (mode SBIE_MV_DLP_ONLY).  Section 2.1 (double-layer kernel), Section
+ * 2.2 (discretisation).  x and y are device FP64 of length n and must not
+ * overlap.  Direct O(Nn^2) evaluation; scratch memory comes from the
+ * stream-ordered allocator and is released before return. */
+enum { SBIE_MV_FULL = 0, SBIE_MV_DLP_ONLY = 1 };
+int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y, int mode,
+                      void *stream);
+
+/* Launch shape of the matvec's pair kernel (chosen by the autotuner):
+ * targets_per_thread in {1, 2, 4, 8}; source_chunks >= 1 splits the source
+ * loop across that many workgroups per target tile (0 = automatic). */
+int stokes_dlp_matvec_set_shape(int targets_per_thread, int source_chunks);
+
+/* Kernel timing of the matvec's pair kernel (the dominant kernel): while
+ * enabled, every launch of it is bracketed by HIP events recorded on the
+ * stream it is launched on.  sbie_kernel_time synchronises those events,
+ * returns the summed duration in milliseconds and the launch count, and
+ * clears the record.  Not thread-safe; meant for benchmarks. */
+int sbie_kernel_timing(int enable);
+int sbie_kernel_time(double *total_ms, int64_t *launches);
+
+/* Block-diagonal preconditioner (Section 4.1.1): one block per pore (its
+ * nodes and its three constraint unknowns) and one block for the wall; each
+ * block is assembled and inverted exactly.  bd_solve computes x = P^{-1} b
+ * (device FP64 length n; x and b must not overlap). */
+typedef struct sbie_bd sbie_bd;
+int bd_factor(const sbie_geom *g, sbie_bd **out, void *stream);
+int bd_solve(const sbie_bd *bd, const double *b, double *x, void *stream);
+int bd_destroy(sbie_bd *bd);
+
+/* Inverse fast multipole method (Section 3): an approximate factorisation of
+ * the H^2 representation A ~ S + U A_coarse V^T (Section 3.1) built from
+ * Chebyshev interpolation with a rank-revealing reduction, eliminated level
+ * by level on the extended sparse system (Section 3.2) with fill-ins between
+ * well-separated boxes compressed to tolerance eps and redirected through
+ * the low-rank bases (Section 3.3).
+ *   eps          relative truncation tolerance on singular values.
+ *   cheb_n       Chebyshev nodes per direction for the initial bases.
+ *   leaf_target  mean number of boundary nodes per non-empty leaf.
+ *   max_depth    cap on the quadtree depth (0 = automatic).
+ *   precision    0 = FP64 factor and apply, 1 = FP32.
+ * ifmm_solve computes x ~ A^{-1} b (device FP64, length n).
+ * Errors: SBIE_UNSUPPORTED if a pore is larger than a leaf box allows;
+ * SBIE_BREAKDOWN on a singular pivot. */
+typedef struct {
+  double eps;
+  int32_t cheb_n;
+  int32_t leaf_target;
+  int32_t max_depth;
+  int32_t precision;
+} ifmm_params;
+typedef struct ifmm_handle ifmm_handle;
+int ifmm_factor(const sbie_geom *g, const ifmm_params *p, ifmm_handle **out,
+                void *stream);
+int ifmm_solve(const ifmm_handle *h, const double *b, double *x, void *stream);
+int ifmm_destroy(ifmm_handle *h);
+/* Statistics of a factorisation (host): levels, leaves, max rank, factor
+ * bytes and factor time in seconds. */
+typedef struct {
+  int32_t levels;
+  int32_t leaves;
+  int32_t max_rank;
+  int32_t reserved;
+  int64_t factor_bytes;
+  double factor_seconds;
+} ifmm_stats;
+int ifmm_get_stats(const ifmm_handle *h, ifmm_stats *s);
+
+/* Flexible GMRES with right preconditioning (Section 4 uses GMRES with a
+ * preconditioner; here the preconditioner is applied on the right and the
+ * stopping test is the true residual ||f - A sigma|| <= tol ||f||).
+ * Arnoldi uses classical Gram-Schmidt applied twice, in FP64.
+ *   f        device FP64 length n (right-hand side).
+ *   sigma    device FP64 length n; the initial guess when use_x0 != 0, and
+ *            the solution on return.
+ *   pc       0 = none, 1 = block-diagonal (bd must be set), 2 = IFMM (ifmm
+ *            must be set).
+ *   res_hist (host, optional) max_iter + 2 doubles: relative residual per
+ *            iteration.
+ * Returns SBIE_OK, SBIE_NOT_CONVERGED (sigma = best iterate) or an error. */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t restart;
+  int32_t pc;
+  int32_t use_x0;
+  const sbie_bd *bd;
+  const ifmm_handle *ifmm;
+  double *res_hist;
+} gmres_params;
+typedef struct {
+  int32_t iters;
+  int32_t status;
+  double rel_res_true;
+  double rel_res_pc;
+  double t_precond_s;
+  double t_matvec_s;
+  double t_arnoldi_s;
+  double t_total_s;
+} gmres_result;
+int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
+                const gmres_params *p, gmres_result *res, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES_IFMM_H */

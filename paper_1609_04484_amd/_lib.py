@@ -1,0 +1,299 @@
+"""ctypes binding of libstokes_ifmm.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module moves the seeded
+geometry to device memory with PyTorch, passes raw device pointers and the
+current HIP stream, and turns status codes into exceptions.  There is no CPU
+fallback: if the library is missing or no GPU is present, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstokes_ifmm.so")
+
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_dp = ctypes.c_void_p
+
+
+class SbieGeom(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64),
+        ("n_pores", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("curve_off", _c_i64p),
+        ("curve_off_dev", ctypes.c_void_p),
+        ("x", _c_dp), ("y", _c_dp),
+        ("nx", _c_dp), ("ny", _c_dp),
+        ("w", _c_dp), ("kappa", _c_dp),
+        ("cx", _c_dp), ("cy", _c_dp),
+        ("radius", _c_dp),
+    ]
+
+
+class IfmmParams(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("cheb_n", ctypes.c_int32),
+        ("leaf_target", ctypes.c_int32),
+        ("max_depth", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class IfmmStats(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("leaves", ctypes.c_int32),
+        ("max_rank", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("factor_bytes", ctypes.c_int64),
+        ("factor_seconds", ctypes.c_double),
+    ]
+
+
+class GmresParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
+        ("pc", ctypes.c_int32),
+        ("use_x0", ctypes.c_int32),
+        ("bd", ctypes.c_void_p),
+        ("ifmm", ctypes.c_void_p),
+        ("res_hist", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class GmresResult(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("rel_res_true", ctypes.c_double),
+        ("rel_res_pc", ctypes.c_double),
+        ("t_precond_s", ctypes.c_double),
+        ("t_matvec_s", ctypes.c_double),
+        ("t_arnoldi_s", ctypes.c_double),
+        ("t_total_s", ctypes.c_double),
+    ]
+
+
+EXPORTS = {
+    "sbie_last_error": (ctypes.c_char_p, []),
+    "stokes_bie_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, ctypes.c_int64,
+                                           _c_dp, ctypes.c_int64, _c_dp, ctypes.c_int64, _c_dp]),
+    "stokes_dlp_matvec": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int, _c_dp]),
+    "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
+    "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "bd_factor": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(ctypes.c_void_p), _c_dp]),
+    "bd_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, _c_dp]),
+    "bd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ifmm_factor": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(IfmmParams),
+                                   ctypes.POINTER(ctypes.c_void_p), _c_dp]),
+    "ifmm_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, _c_dp]),
+    "ifmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ifmm_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(IfmmStats)]),
+    "gmres_solve": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp,
+                                   ctypes.POINTER(GmresParams), ctypes.POINTER(GmresResult), _c_dp]),
+}
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARGUMENT", -2: "INVALID_GEOMETRY",
+          -3: "OUT_OF_MEMORY", -4: "HIP_ERROR", -5: "BREAKDOWN", -6: "UNSUPPORTED"}
+
+_lib = None
+
+
+class SbieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1609_04484_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(code: int) -> int:
+    if code < 0:
+        raise SbieError(code, load().sbie_last_error().decode())
+    return code
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return t.data_ptr()
+
+
+class DeviceGeometry:
+    """A geometry resident in device memory plus its C descriptor."""
+
+    def __init__(self, geom, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available: the HIP library needs an MI355X")
+        self.geom = geom
+        dev = torch.device(device)
+        to = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        self.t = {k: to(getattr(geom, k)) for k in ("x", "y", "nx", "ny", "w", "kappa")}
+        m = geom.n_pores
+        pore = lambda a: to(a) if m else torch.zeros(1, dtype=torch.float64, device=dev)
+        self.t["cx"] = pore(geom.cx)
+        self.t["cy"] = pore(geom.cy)
+        self.t["radius"] = pore(geom.radius)
+        self.off_host = np.ascontiguousarray(geom.curve_off, dtype=np.int64)
+        self.off_dev = torch.as_tensor(self.off_host).to(dev)
+        self.n = geom.n_unknowns
+        self.c = SbieGeom(
+            n_nodes=geom.n_nodes, n_pores=m, reserved=0,
+            curve_off=self.off_host.ctypes.data_as(_c_i64p),
+            curve_off_dev=self.off_dev.data_ptr(),
+            **{k: v.data_ptr() for k, v in self.t.items()},
+        )
+
+    def vector(self, a) -> torch.Tensor:
+        return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.t["x"].device).contiguous()
+
+
+def matvec(dg: DeviceGeometry, x: torch.Tensor, mode: int = 0, out=None, stream=None):
+    y = torch.empty_like(x) if out is None else out
+    check(load().stokes_dlp_matvec(ctypes.byref(dg.c), _ptr(x), _ptr(y), mode, _stream(stream)))
+    return y
+
+
+def set_matvec_shape(targets_per_thread: int, source_chunks: int = 0):
+    check(load().stokes_dlp_matvec_set_shape(targets_per_thread, source_chunks))
+
+
+def kernel_timing(enable: bool):
+    """Start or stop event bracketing of the matvec's pair kernel."""
+    check(load().sbie_kernel_timing(int(enable)))
+
+
+def kernel_time():
+    """(total milliseconds, launches) of the pair kernel since the last call."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    check(load().sbie_kernel_time(ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def assemble(dg: DeviceGeometry, rows, cols, stream=None) -> torch.Tensor:
+    dev = dg.t["x"].device
+    r = torch.as_tensor(np.asarray(rows, dtype=np.int64)).to(dev)
+    c = torch.as_tensor(np.asarray(cols, dtype=np.int64)).to(dev)
+    out = torch.empty((c.numel(), r.numel()), dtype=torch.float64, device=dev)
+    check(load().stokes_bie_assemble(ctypes.byref(dg.c), _ptr(r), r.numel(), _ptr(c),
+                                     c.numel(), _ptr(out), r.numel(), _stream(stream)))
+    return out.t()  # column-major storage -> (nr, nc) view
+
+
+class BlockDiagonal:
+    def __init__(self, dg: DeviceGeometry, stream=None):
+        self.dg = dg
+        h = ctypes.c_void_p()
+        check(load().bd_factor(ctypes.byref(dg.c), ctypes.byref(h), _stream(stream)))
+        self.h = h
+
+    def solve(self, b: torch.Tensor, stream=None) -> torch.Tensor:
+        x = torch.empty_like(b)
+        check(load().bd_solve(self.h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def close(self):
+        if self.h:
+            load().bd_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class IFMM:
+    def __init__(self, dg: DeviceGeometry, eps=1e-6, cheb_n=10, leaf_target=64,
+                 max_depth=0, precision=0, stream=None):
+        self.dg = dg
+        p = IfmmParams(eps=eps, cheb_n=cheb_n, leaf_target=leaf_target,
+                       max_depth=max_depth, precision=precision)
+        h = ctypes.c_void_p()
+        check(load().ifmm_factor(ctypes.byref(dg.c), ctypes.byref(p), ctypes.byref(h),
+                                 _stream(stream)))
+        self.h = h
+
+    def solve(self, b: torch.Tensor, stream=None) -> torch.Tensor:
+        x = torch.empty_like(b)
+        check(load().ifmm_solve(self.h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def stats(self) -> dict:
+        s = IfmmStats()
+        check(load().ifmm_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in IfmmStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.h:
+            load().ifmm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class SolveResult:
+    sigma: torch.Tensor
+    iters: int
+    status: int
+    rel_res_true: float
+    rel_res_pc: float
+    t_precond_s: float
+    t_matvec_s: float
+    t_arnoldi_s: float
+    t_total_s: float
+    history: np.ndarray
+
+
+def gmres(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000,
+          restart=0, x0: torch.Tensor | None = None, stream=None) -> SolveResult:
+    """FGMRES solve of A sigma = f; pc is None, a BlockDiagonal or an IFMM."""
+    sigma = torch.zeros_like(f) if x0 is None else x0.clone()
+    hist = np.zeros(max_iter + 2)
+    kind = 0 if pc is None else (1 if isinstance(pc, BlockDiagonal) else 2)
+    p = GmresParams(tol=tol, max_iter=max_iter, restart=restart, pc=kind,
+                    use_x0=int(x0 is not None),
+                    bd=pc.h.value if kind == 1 else None,
+                    ifmm=pc.h.value if kind == 2 else None,
+                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    r = GmresResult()
+    check(load().gmres_solve(ctypes.byref(dg.c), _ptr(f), _ptr(sigma), ctypes.byref(p),
+                             ctypes.byref(r), _stream(stream)))
+    return SolveResult(sigma, r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
+                       r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, hist[:r.iters + 1].copy())

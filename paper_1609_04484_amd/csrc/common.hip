@@ -1,0 +1,51 @@
+// Error plumbing, descriptor validation and the per-device rocBLAS handle.
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace sbie {
+
+namespace {
+thread_local std::string g_last_error;
+std::mutex g_blas_mu;
+std::vector<rocblas_handle> g_blas;  // one per device, created on first use
+}  // namespace
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+rocblas_handle blas_handle(hipStream_t stream) {
+  int dev = 0;
+  SBIE_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  if ((int)g_blas.size() <= dev) g_blas.resize(dev + 1, nullptr);
+  if (!g_blas[dev]) SBIE_BLAS(rocblas_create_handle(&g_blas[dev]));
+  SBIE_BLAS(rocblas_set_stream(g_blas[dev], stream));
+  return g_blas[dev];
+}
+
+void validate_geom(const sbie_geom *g) {
+  if (!g) fail(SBIE_INVALID_ARGUMENT, "null geometry descriptor");
+  if (g->n_nodes <= 0) fail(SBIE_INVALID_ARGUMENT, "n_nodes must be positive");
+  if (g->n_pores < 0) fail(SBIE_INVALID_ARGUMENT, "n_pores must be >= 0");
+  if (!g->curve_off || !g->curve_off_dev)
+    fail(SBIE_INVALID_ARGUMENT, "curve offsets missing");
+  if (!g->x || !g->y || !g->nx || !g->ny || !g->w || !g->kappa)
+    fail(SBIE_INVALID_ARGUMENT, "node arrays missing");
+  if (g->n_pores > 0 && (!g->cx || !g->cy || !g->radius))
+    fail(SBIE_INVALID_ARGUMENT, "pore arrays missing");
+  const int64_t *off = g->curve_off;
+  if (off[0] != 0 || off[g->n_pores + 1] != g->n_nodes)
+    fail(SBIE_INVALID_ARGUMENT, "curve offsets must run from 0 to n_nodes");
+  for (int k = 0; k <= g->n_pores; ++k)
+    if (off[k + 1] < off[k]) fail(SBIE_INVALID_ARGUMENT, "curve offsets decrease");
+  for (int k = 0; k < g->n_pores; ++k)
+    if (off[k + 1] - off[k] < 3)
+      fail(SBIE_INVALID_GEOMETRY, "pore %d has fewer than 3 nodes", k);
+}
+
+}  // namespace sbie
+
+extern "C" const char *sbie_last_error(void) {
+  return sbie::g_last_error.c_str();
+}

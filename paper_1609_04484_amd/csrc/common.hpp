@@ -1,0 +1,163 @@
+// Internal helpers shared by the library's translation units: status and
+// error-message plumbing, HIP error checks, small RAII device buffers, the
+// per-device rocBLAS handle and the geometry-derived constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/stokes_ifmm.h"
+
+namespace sbie {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// A failure inside the library: carries a status code to the C ABI.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &msg);
+
+[[noreturn]] inline void fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error(code, buf);
+}
+
+#define SBIE_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      ::sbie::fail(SBIE_HIP_ERROR, "%s failed: %s (%s:%d)", #call,            \
+                   hipGetErrorString(e_), __FILE__, __LINE__);                \
+  } while (0)
+
+#define SBIE_BLAS(call)                                                       \
+  do {                                                                        \
+    rocblas_status s_ = (call);                                               \
+    if (s_ != rocblas_status_success)                                         \
+      ::sbie::fail(SBIE_HIP_ERROR, "%s failed: rocblas status %d (%s:%d)",    \
+                   #call, (int)s_, __FILE__, __LINE__);                       \
+  } while (0)
+
+#define SBIE_LAUNCH_CHECK() SBIE_HIP(hipGetLastError())
+
+// Run a body and translate exceptions into a status code.
+template <class F>
+int guarded(F &&f) {
+  try {
+    set_last_error("");
+    return f();
+  } catch (const Error &e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_last_error("host allocation failed");
+    return SBIE_OUT_OF_MEMORY;
+  } catch (const std::exception &e) {
+    set_last_error(e.what());
+    return SBIE_INVALID_ARGUMENT;
+  }
+}
+
+// Device buffer owned by the library (plain hipMalloc; used for long-lived
+// handles such as factorisations).
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(SBIE_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Scratch from the stream-ordered allocator, released on the same stream.
+template <class T>
+struct StreamBuf {
+  T *p = nullptr;
+  hipStream_t s = nullptr;
+  StreamBuf(size_t count, hipStream_t st) : s(st) {
+    if (count == 0) return;
+    if (hipMallocAsync((void **)&p, count * sizeof(T), s) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(SBIE_OUT_OF_MEMORY, "hipMallocAsync of %zu bytes failed", count * sizeof(T));
+    }
+  }
+  StreamBuf(const StreamBuf &) = delete;
+  StreamBuf &operator=(const StreamBuf &) = delete;
+  ~StreamBuf() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+rocblas_handle blas_handle(hipStream_t stream);
+
+// Checks on the geometry descriptor that need no device access.
+void validate_geom(const sbie_geom *g);
+
+inline int64_t n_unknowns(const sbie_geom *g) {
+  return 2 * g->n_nodes + 3 * (int64_t)g->n_pores;
+}
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Matvec internals (matvec.hip), reused by the solvers.
+// ---------------------------------------------------------------------------
+struct MatvecWork {
+  double *src = nullptr;     // packed source records, 8 doubles per node
+  double *psrc = nullptr;    // packed pore records, 8 doubles per pore
+  double *part = nullptr;    // partial sums [chunks][2][Nn]
+  double *scal = nullptr;    // [0] = flux functional, [1] = wall length
+  int chunks = 0;            // source chunks of the pair kernel
+  int pchunks = 0;           // pore chunks of the completion kernel
+  int tpt = 4;               // targets per thread
+  size_t doubles() const;
+};
+
+// Plan the launch shape and the scratch size (in doubles) for a geometry.
+MatvecWork plan_matvec(const sbie_geom *g);
+size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g);
+void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base);
+void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
+                MatvecWork &w, hipStream_t s);
+
+// Wall length |Gamma_0| into *out (device scalar).
+void wall_length(const sbie_geom *g, double *out, hipStream_t s);
+
+}  // namespace sbie

@@ -1,0 +1,19 @@
+// Preconditioner dispatch used by the Krylov solver.
+#pragma once
+
+#include "common.hpp"
+
+namespace sbie {
+
+void bd_apply(const sbie_bd *bd, const double *b, double *x, hipStream_t s);
+void ifmm_apply(const ifmm_handle *h, const double *b, double *x, hipStream_t s);
+
+inline void precond_apply(const gmres_params *p, const double *in, double *out,
+                          hipStream_t s) {
+  if (p->pc == 1)
+    bd_apply(p->bd, in, out, s);
+  else
+    ifmm_apply(p->ifmm, in, out, s);
+}
+
+}  // namespace sbie
