@@ -210,8 +210,16 @@ def test_gmres_exact_start_and_cap(lib, tiny):
     assert r.iters == 0 and r.status == 0
     r = lib.gmres(dg, dg.vector(f), tol=1e-10, max_iter=1)
     assert r.status == 1 and r.iters == 1
-    r = lib.gmres(dg, dg.vector(f), tol=1e-10, restart=15)
+    # restarted GMRES(60) converges, like the oracle's restarted FGMRES
+    r = lib.gmres(dg, dg.vector(f), tol=1e-10, restart=60, max_iter=600)
+    ref = solve.fgmres(lambda v: a @ v, f, tol=1e-10, restart=60, max_iter=600)
+    assert ref.converged
     assert r.status == 0 and r.rel_res_true < 1e-10
+    assert abs(r.iters - ref.iters) <= 5
+    # short restarts stagnate on this system on both sides
+    r = lib.gmres(dg, dg.vector(f), tol=1e-10, restart=15, max_iter=300)
+    ref = solve.fgmres(lambda v: a @ v, f, tol=1e-10, restart=15, max_iter=300)
+    assert r.status == 1 and not ref.converged
 
 
 def test_gmres_nonfinite_rhs_is_an_error(lib, tiny):
