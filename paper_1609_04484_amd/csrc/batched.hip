@@ -1,0 +1,590 @@
+// Variable-size batched dense kernels (double and float instantiations).
+#include <cstring>
+
+#include "batched.hpp"
+
+namespace sbie {
+
+// ----------------------------------------------------------------------------
+// Descriptor staging
+// ----------------------------------------------------------------------------
+
+Stager::Stager(size_t bytes) : cap(bytes) {
+  SBIE_HIP(hipHostMalloc((void **)&host, bytes, hipHostMallocDefault));
+  dev.alloc(bytes);
+}
+
+Stager::~Stager() {
+  if (host) (void)hipHostFree(host);
+}
+
+void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (need > cap) fail(SBIE_OUT_OF_MEMORY, "descriptor batch of %zu bytes exceeds staging", bytes);
+  if (used + need > cap) {
+    // every earlier copy and every kernel reading earlier descriptors must
+    // finish before the rings are reused
+    SBIE_HIP(hipStreamSynchronize(s));
+    used = 0;
+  }
+  std::memcpy(host + used, src, bytes);
+  SBIE_HIP(hipMemcpyAsync(dev.p + used, host + used, bytes, hipMemcpyHostToDevice, s));
+  void *d = dev.p + used;
+  used += need;
+  return d;
+}
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// GEMM: one 64 x 64 output tile per workgroup, 256 threads, 4 x 4 per thread
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void gemm_tiles(const GemmDesc<T> *__restrict__ descs,
+                                                  const int2 *__restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const GemmDesc<T> d = descs[tl.x];
+  const int tiles_m = (d.m + 63) >> 6;
+  const int row0 = (tl.y % tiles_m) * 64;
+  const int col0 = (tl.y / tiles_m) * 64;
+  __shared__ T As[16][65];
+  __shared__ T Bs[16][65];
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int r, kk;
+      if (!d.ta) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
+      const int gi = row0 + r, gk = k0 + kk;
+      T v = T(0);
+      if (gi < d.m && gk < d.k)
+        v = d.ta ? d.A[gk + (size_t)gi * d.lda] : d.A[gi + (size_t)gk * d.lda];
+      As[kk][r] = v;
+      int c;
+      if (!d.tb) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
+      const int gj = col0 + c, gk2 = k0 + kk;
+      T w = T(0);
+      if (gj < d.n && gk2 < d.k)
+        w = d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb];
+      Bs[kk][c] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = row0 + tr + 16 * i;
+    if (r >= d.m) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = col0 + tc + 16 * j;
+      if (c >= d.n) continue;
+      T *p = d.C + r + (size_t)c * d.ldc;
+      T v = d.alpha * acc[i][j];
+      if (d.beta != T(0)) v = fma(d.beta, *p, v);
+      *p = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// GEMV: one workgroup per descriptor (at most 64 rows)
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__ descs,
+                                                 const GemvTerm<T> *__restrict__ terms) {
+  const GemvDesc<T> d = descs[blockIdx.x];
+  __shared__ T part[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  T acc = T(0);        // trans = 0: this thread's partial for row `lane`
+  T accw[16];          // trans = 1: wave-owned rows wv, wv + 4, ...
+#pragma unroll
+  for (int q = 0; q < 16; ++q) accw[q] = T(0);
+  for (int t = d.t0; t < d.t0 + d.nt; ++t) {
+    const GemvTerm<T> tm = terms[t];
+    if (!tm.trans) {
+      T s = T(0);
+      if (lane < d.rows)
+        for (int c = wv; c < tm.cols; c += 4) s = fma(tm.A[lane + (size_t)c * tm.lda], tm.x[c], s);
+      acc = fma(tm.alpha, s, acc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = wv + 4 * q;
+        if (r >= d.rows) break;
+        const T *col = tm.A + (size_t)r * tm.lda;
+        T s = T(0);
+        for (int c = lane; c < tm.cols; c += 64) s = fma(col[c], tm.x[c], s);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if (lane == 0) accw[q] = fma(tm.alpha, s, accw[q]);
+      }
+    }
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = wv + 4 * q;
+      if (r < d.rows) part[wv][r] += accw[q];
+    }
+  }
+  __syncthreads();
+  if (tid < d.rows) {
+    const T v = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    T *y = d.y + tid;
+    *y = d.beta != T(0) ? fma(d.beta, *y, v) : v;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Block copies: blockIdx.x = descriptor, blockIdx.y = 16-column slab
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void copy_desc(const CopyDesc<T> *__restrict__ descs) {
+  const CopyDesc<T> d = descs[blockIdx.x];
+  const int c0 = blockIdx.y * 16;
+  if (c0 >= d.cols) return;
+  const int c1 = c0 + 16 < d.cols ? c0 + 16 : d.cols;
+  for (int c = c0; c < c1; ++c)
+    for (int r = threadIdx.x; r < d.rows; r += blockDim.x) {
+      const T v = d.trans ? d.src[c + (size_t)r * d.lds] : d.src[r + (size_t)c * d.lds];
+      T *p = d.dst + r + (size_t)c * d.ldd;
+      *p = d.acc ? fma(d.alpha, v, *p) : d.alpha * v;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void norm_desc(const NormDesc<T> *__restrict__ descs,
+                                                 double *__restrict__ out) {
+  const NormDesc<T> d = descs[blockIdx.x];
+  double s = 0.0;
+  for (int c = 0; c < d.cols; ++c)
+    for (int r = threadIdx.x; r < d.rows; r += 256) {
+      const double v = (double)d.A[r + (size_t)c * d.lda];
+      s = fma(v, v, s);
+    }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void normalize_cols(T *A, int lda, int rows) {
+  T *col = A + (size_t)blockIdx.x * lda;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) s = fma((double)col[r], (double)col[r], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double nrm = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+  const T scale = nrm > 0.0 ? T(1.0 / nrm) : T(0);
+  for (int r = threadIdx.x; r < rows; r += 256) col[r] *= scale;
+}
+
+// ----------------------------------------------------------------------------
+// Gauss-Jordan inversion with partial pivoting, one workgroup per matrix
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void gj_kernel(T *const *__restrict__ ptrs,
+                                                 const int *__restrict__ ns,
+                                                 int32_t *__restrict__ info) {
+  extern __shared__ unsigned char shraw[];
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const int b = blockIdx.x;
+  const int n = ns[b];
+  T *A = ptrs[b];
+  T *rowk = reinterpret_cast<T *>(shraw);
+  T *fcol = rowk + n;
+  int *ipiv = reinterpret_cast<int *>(fcol + n);
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += 256) {
+      const double v = fabs((double)A[i + (size_t)k * n]);
+      if (v > best) { best = v; bi = i; }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double ov = red_v[tid + s];
+        const int oi = red_i[tid + s];
+        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = ov;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const double pv = red_v[0];
+    const int p = red_i[0];
+    __syncthreads();
+    if (!(pv > 0.0) || !isfinite(pv)) {
+      if (tid == 0) info[b] = k + 1;
+      return;
+    }
+    if (tid == 0) ipiv[k] = p;
+    if (p != k)
+      for (int j = tid; j < n; j += 256) {
+        const T t = A[k + (size_t)j * n];
+        A[k + (size_t)j * n] = A[p + (size_t)j * n];
+        A[p + (size_t)j * n] = t;
+      }
+    __syncthreads();
+    const T invd = T(1) / A[k + (size_t)k * n];
+    for (int j = tid; j < n; j += 256) rowk[j] = (j == k ? T(1) : A[k + (size_t)j * n]) * invd;
+    for (int i = tid; i < n; i += 256) fcol[i] = i == k ? T(0) : A[i + (size_t)k * n];
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      const T f = fcol[i];
+      if (i == k) {
+        for (int j = 0; j < n; ++j) A[i + (size_t)j * n] = rowk[j];
+      } else {
+        for (int j = 0; j < n; ++j) {
+          const T a = j == k ? T(0) : A[i + (size_t)j * n];
+          A[i + (size_t)j * n] = fma(-f, rowk[j], a);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = ipiv[k];
+    if (p != k)
+      for (int i = tid; i < n; i += 256) {
+        const T t = A[i + (size_t)k * n];
+        A[i + (size_t)k * n] = A[i + (size_t)p * n];
+        A[i + (size_t)p * n] = t;
+      }
+    __syncthreads();
+  }
+  if (tid == 0) info[b] = 0;
+}
+
+// ----------------------------------------------------------------------------
+// Truncated pivoted Gram-Schmidt (rank-revealing), one workgroup per problem
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__ descs) {
+  extern __shared__ unsigned char shraw[];
+  const PgsDesc<T> d = descs[blockIdx.x];
+  double *norms = reinterpret_cast<double *>(shraw);   // c
+  double *dots = norms + d.c;                           // rmax
+  T *q = reinterpret_cast<T *>(dots + d.rmax);          // m
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  __shared__ int s_stop;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = wv; j < d.c; j += 4) {
+    const T *col = d.R + (size_t)j * d.ldr;
+    double s = 0.0;
+    for (int i = lane; i < d.m; i += 64) s = fma((double)col[i], (double)col[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) norms[j] = s;
+  }
+  __syncthreads();
+  const double tol2 = d.tol * d.tol;
+  int k = 0;
+  int guard = 0;
+  while (d.r0 + k < d.rmax && guard < d.c + d.rmax) {
+    ++guard;
+    double best = -1.0;
+    int bi = 0;
+    for (int j = tid; j < d.c; j += 256)
+      if (norms[j] > best) { best = norms[j]; bi = j; }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double ov = red_v[tid + s];
+        const int oi = red_i[tid + s];
+        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = ov;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const double vmax = red_v[0];
+    const int p = red_i[0];
+    __syncthreads();
+    if (!(vmax > tol2)) break;
+    for (int i = tid; i < d.m; i += 256) q[i] = d.R[i + (size_t)p * d.ldr];
+    __syncthreads();
+    const int rc = d.r0 + k;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int col = wv; col < rc; col += 4) {
+        const T *w = d.W + (size_t)col * d.ldw;
+        double s = 0.0;
+        for (int i = lane; i < d.m; i += 64) s = fma((double)w[i], (double)q[i], s);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if (lane == 0) dots[col] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < d.m; i += 256) {
+        double v = (double)q[i];
+        for (int col = 0; col < rc; ++col) v = fma(-(double)d.W[i + (size_t)col * d.ldw], dots[col], v);
+        q[i] = (T)v;
+      }
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int i = tid; i < d.m; i += 256) s = fma((double)q[i], (double)q[i], s);
+    red_v[tid] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red_v[tid] += red_v[tid + st];
+      __syncthreads();
+    }
+    const double nq = red_v[0];
+    __syncthreads();
+    if (tid == 0) s_stop = (nq <= 1e-4 * vmax || !(nq > 0.0)) ? 1 : 0;
+    __syncthreads();
+    if (s_stop) {
+      // numerically inside the current span: retire the column
+      if (tid == 0) norms[p] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double inv = 1.0 / sqrt(nq);
+    T *wn = d.W + (size_t)rc * d.ldw;
+    for (int i = tid; i < d.m; i += 256) {
+      const T v = (T)((double)q[i] * inv);
+      q[i] = v;
+      wn[i] = v;
+    }
+    __syncthreads();
+    ++k;
+    for (int j = wv; j < d.c; j += 4) {
+      T *col = d.R + (size_t)j * d.ldr;
+      double dt = 0.0;
+      for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);
+      for (int o = 32; o > 0; o >>= 1) dt += __shfl_down(dt, o, 64);
+      dt = __shfl(dt, 0, 64);
+      double sq = 0.0;
+      for (int i = lane; i < d.m; i += 64) {
+        const T v = (T)((double)col[i] - dt * (double)q[i]);
+        col[i] = v;
+        sq = fma((double)v, (double)v, sq);
+      }
+      for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
+      if (lane == 0) norms[j] = sq;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *d.count = k;
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+template <class T>
+__global__ void gaussian_kernel(T *out, size_t n, uint64_t seed) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t a = splitmix64(seed * 0x100000001B3ull + 2 * i);
+  const uint64_t b = splitmix64(seed * 0x100000001B3ull + 2 * i + 1);
+  const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+  out[i] = (T)(sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2));
+}
+
+template <class T>
+__global__ void fill_kernel(T *out, size_t n, T v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+template <class A, class B>
+__global__ void convert_kernel(const A *src, B *dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (B)src[i];
+}
+
+}  // namespace
+
+template <class T>
+void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) {
+  std::vector<GemmDesc<T>> keep;
+  std::vector<int2> tiles;
+  for (const auto &g : d) {
+    if (g.m <= 0 || g.n <= 0) continue;
+    const int id = (int)keep.size();
+    keep.push_back(g);
+    const int nt = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+    for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(id, t));
+  }
+  if (tiles.empty()) return;
+  auto *dd = (const GemmDesc<T> *)st.put(keep.data(), keep.size() * sizeof(GemmDesc<T>), s);
+  for (size_t t0 = 0; t0 < tiles.size(); t0 += 1u << 20) {
+    const size_t nt = std::min(tiles.size() - t0, size_t(1) << 20);
+    auto *td = (const int2 *)st.put(tiles.data() + t0, nt * sizeof(int2), s);
+    gemm_tiles<T><<<(unsigned)nt, 256, 0, s>>>(dd, td);
+    SBIE_LAUNCH_CHECK();
+  }
+}
+
+template <class T>
+void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T> *t, int nd, int, hipStream_t s) {
+  if (nd == 0) return;
+  gemv_desc<T><<<nd, 256, 0, s>>>(d, t);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<T>> &t,
+                  Stager &st, hipStream_t s) {
+  if (d.empty()) return;
+  auto *tt = (const GemvTerm<T> *)st.put(t.data(), std::max<size_t>(1, t.size()) * sizeof(GemvTerm<T>), s);
+  auto *dd = (const GemvDesc<T> *)st.put(d.data(), d.size() * sizeof(GemvDesc<T>), s);
+  gemv_launch<T>(dd, tt, (int)d.size(), 64, s);
+}
+
+template <class T>
+void copy_launch(const CopyDesc<T> *d, int nd, int max_cols, hipStream_t s) {
+  if (nd == 0 || max_cols == 0) return;
+  dim3 grid(nd, ceil_div(max_cols, 16));
+  copy_desc<T><<<grid, 256, 0, s>>>(d);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s) {
+  std::vector<CopyDesc<T>> keep;
+  int max_cols = 0;
+  for (const auto &c : d)
+    if (c.rows > 0 && c.cols > 0) {
+      keep.push_back(c);
+      max_cols = std::max(max_cols, c.cols);
+    }
+  if (keep.empty()) return;
+  for (size_t b0 = 0; b0 < keep.size(); b0 += 60000) {
+    const size_t nb = std::min(keep.size() - b0, size_t(60000));
+    auto *dd = (const CopyDesc<T> *)st.put(keep.data() + b0, nb * sizeof(CopyDesc<T>), s);
+    copy_launch<T>(dd, (int)nb, max_cols, s);
+  }
+}
+
+template <class T>
+void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
+                     int32_t *info_dev, Stager &st, hipStream_t s) {
+  if (ptrs.empty()) return;
+  int mx = 1;
+  for (int n : ns) mx = std::max(mx, n);
+  const size_t shmem = 2 * mx * sizeof(T) + mx * sizeof(int);
+  if (shmem > 56 * 1024) fail(SBIE_UNSUPPORTED, "dense block of size %d too large to invert", mx);
+  auto *pd = (T *const *)st.put(ptrs.data(), ptrs.size() * sizeof(T *), s);
+  auto *nd = (const int *)st.put(ns.data(), ns.size() * sizeof(int), s);
+  gj_kernel<T><<<(unsigned)ptrs.size(), 256, shmem, s>>>(pd, nd, info_dev);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void norms_batched(const std::vector<NormDesc<T>> &d, double *out_dev, Stager &st,
+                   hipStream_t s) {
+  if (d.empty()) return;
+  auto *dd = (const NormDesc<T> *)st.put(d.data(), d.size() * sizeof(NormDesc<T>), s);
+  norm_desc<T><<<(unsigned)d.size(), 256, 0, s>>>(dd, out_dev);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void normalize_columns(T *A, int lda, int rows, int cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return;
+  normalize_cols<T><<<cols, 256, 0, s>>>(A, lda, rows);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s) {
+  if (d.empty()) return;
+  size_t shmem = 0;
+  for (const auto &p : d) {
+    const size_t b = (size_t)p.c * sizeof(double) + (size_t)p.rmax * sizeof(double) +
+                     (size_t)p.m * sizeof(T);
+    shmem = std::max(shmem, b);
+  }
+  if (shmem > 60 * 1024)
+    fail(SBIE_UNSUPPORTED, "rank-revealing step too large (%zu bytes of LDS)", shmem);
+  auto *dd = (const PgsDesc<T> *)st.put(d.data(), d.size() * sizeof(PgsDesc<T>), s);
+  pgs_kernel<T><<<(unsigned)d.size(), 256, shmem, s>>>(dd);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void gaussian_fill(T *out, size_t n, uint64_t seed, hipStream_t s) {
+  if (n == 0) return;
+  gaussian_kernel<T><<<ceil_div((int64_t)n, 256), 256, 0, s>>>(out, n, seed);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class T>
+void fill_value(T *out, size_t n, T v, hipStream_t s) {
+  if (n == 0) return;
+  fill_kernel<T><<<ceil_div((int64_t)n, 256), 256, 0, s>>>(out, n, v);
+  SBIE_LAUNCH_CHECK();
+}
+
+template <class A, class B>
+void convert(const A *src, B *dst, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  convert_kernel<A, B><<<ceil_div((int64_t)n, 256), 256, 0, s>>>(src, dst, n);
+  SBIE_LAUNCH_CHECK();
+}
+
+#define SBIE_INST(T)                                                                     \
+  template void gemm_batched<T>(const std::vector<GemmDesc<T>> &, Stager &, hipStream_t); \
+  template void gemv_batched<T>(const std::vector<GemvDesc<T>> &,                        \
+                                const std::vector<GemvTerm<T>> &, Stager &, hipStream_t); \
+  template void gemv_launch<T>(const GemvDesc<T> *, const GemvTerm<T> *, int, int,       \
+                               hipStream_t);                                             \
+  template void copy_batched<T>(const std::vector<CopyDesc<T>> &, Stager &, hipStream_t); \
+  template void copy_launch<T>(const CopyDesc<T> *, int, int, hipStream_t);              \
+  template void inverse_batched<T>(const std::vector<T *> &, const std::vector<int> &,   \
+                                   int32_t *, Stager &, hipStream_t);                    \
+  template void norms_batched<T>(const std::vector<NormDesc<T>> &, double *, Stager &,   \
+                                 hipStream_t);                                           \
+  template void normalize_columns<T>(T *, int, int, int, hipStream_t);                   \
+  template void pgs_batched<T>(const std::vector<PgsDesc<T>> &, Stager &, hipStream_t);  \
+  template void gaussian_fill<T>(T *, size_t, uint64_t, hipStream_t);                   \
+  template void fill_value<T>(T *, size_t, T, hipStream_t);
+
+SBIE_INST(double)
+SBIE_INST(float)
+template void fill_value<int>(int *, size_t, int, hipStream_t);
+template void convert<double, float>(const double *, float *, size_t, hipStream_t);
+template void convert<float, double>(const float *, double *, size_t, hipStream_t);
+template void convert<double, double>(const double *, double *, size_t, hipStream_t);
+
+}  // namespace sbie

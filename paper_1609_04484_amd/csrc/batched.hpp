@@ -1,0 +1,130 @@
+// Variable-size batched dense kernels used by the IFMM factorisation and
+// solve, templated on the working precision (double or float).
+#pragma once
+
+#include "common.hpp"
+
+namespace sbie {
+
+// C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n, column-major.
+template <class T>
+struct GemmDesc {
+  int m, n, k;
+  int ta, tb;
+  const T *A;
+  int lda;
+  const T *B;
+  int ldb;
+  T *C;
+  int ldc;
+  T alpha, beta;
+};
+
+// One term of a multi-term GEMV: alpha op(A) x with op(A) rows x cols.
+template <class T>
+struct GemvTerm {
+  const T *A;
+  const T *x;
+  int lda, cols, trans;
+  T alpha;
+};
+
+// y (rows) = beta y + sum of terms [t0, t0 + nt)
+template <class T>
+struct GemvDesc {
+  T *y;
+  int rows;
+  int t0, nt;
+  T beta;
+};
+
+// dst = alpha op(src) (rows x cols of the destination), optionally
+// accumulated (acc != 0: dst += alpha op(src)).
+template <class T>
+struct CopyDesc {
+  const T *src;
+  int lds;
+  T *dst;
+  int ldd;
+  int rows, cols;
+  int trans, acc;
+  T alpha;
+};
+
+// Staging of host-built descriptor arrays into device memory: a pinned host
+// ring and a device ring, both reset at synchronisation points.
+struct Stager {
+  char *host = nullptr;
+  DevBuf<char> dev;
+  size_t cap = 0, used = 0;
+  explicit Stager(size_t bytes);
+  ~Stager();
+  Stager(const Stager &) = delete;
+  Stager &operator=(const Stager &) = delete;
+  // copy bytes to the device ring (stream-ordered); returns the device address
+  void *put(const void *src, size_t bytes, hipStream_t s);
+  void reset() { used = 0; }
+};
+
+template <class T>
+void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s);
+template <class T>
+void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<T>> &t,
+                  Stager &st, hipStream_t s);
+// Device-resident descriptor arrays (prepared once, launched many times).
+template <class T>
+void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T> *t, int nd, int max_rows,
+                 hipStream_t s);
+template <class T>
+void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s);
+template <class T>
+void copy_launch(const CopyDesc<T> *d, int nd, int max_rows, hipStream_t s);
+
+// In-place inverses (Gauss-Jordan with partial pivoting); ptrs[b] -> n_b x n_b
+// column-major matrix with leading dimension n_b; info[b] != 0 = singular.
+template <class T>
+void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
+                     int32_t *info_dev, Stager &st, hipStream_t s);
+
+// Frobenius norms of blocks (rows x cols, ld) into out[b] (double).
+template <class T>
+struct NormDesc {
+  const T *A;
+  int lda, rows, cols;
+};
+template <class T>
+void norms_batched(const std::vector<NormDesc<T>> &d, double *out_dev, Stager &st,
+                   hipStream_t s);
+
+// Scale each column of blocks to unit norm (zero columns left as zero).
+template <class T>
+void normalize_columns(T *A, int lda, int rows, int cols, hipStream_t s);
+
+// Truncated pivoted Gram-Schmidt: R (m x c) holds candidate columns already
+// projected against W[:, :r0]; new orthonormal columns (residual column norm
+// above tol) are appended to W starting at column r0, at most rmax - r0 of
+// them; their number is written to *count.
+template <class T>
+struct PgsDesc {
+  T *R;
+  int ldr, m, c;
+  T *W;
+  int ldw, r0, rmax;
+  double tol;
+  int *count;
+};
+template <class T>
+void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s);
+
+// Standard normal numbers from a counter-based generator (splitmix64 hash of
+// (seed, index) -> two uniforms -> Box-Muller).
+template <class T>
+void gaussian_fill(T *out, size_t n, uint64_t seed, hipStream_t s);
+
+template <class T>
+void fill_value(T *out, size_t n, T v, hipStream_t s);
+
+template <class Tsrc, class Tdst>
+void convert(const Tsrc *src, Tdst *dst, size_t n, hipStream_t s);
+
+}  // namespace sbie

@@ -1,0 +1,102 @@
+"""GPU IFMM (Section 3) through the C ABI.
+
+The IFMM is an approximate inverse, so its parity is checked on what the
+method fixes (Section 3.3: tunable accuracy eps): the error of one
+application against the dense LU solution follows eps, it is exact when no
+box pair is well separated, and as a preconditioner FGMRES reaches the LU
+solution to the stated tolerance in about as many iterations as with the
+oracle's IFMM.
+"""
+import numpy as np
+import pytest
+
+from oracle import dlp, ifmm, solve
+from stokes_inputs import make_geometry, poiseuille_rhs, random_vector, stokeslet_rotlet_rhs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1609_04484_amd as p
+    p.load()
+    return p
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    g = make_geometry("tiny", 1)
+    a = dlp.assemble(g)
+    f, _ = stokeslet_rotlet_rhs(g, 1)
+    return g, a, f, solve.lu_solve(a, f)
+
+
+def rel(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def test_ifmm_factor_and_apply_tiny(lib, tiny):
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    p = lib.IFMM(dg, eps=1e-6, cheb_n=10)
+    st = p.stats()
+    assert st["levels"] >= 3 and st["leaves"] > 4 and st["max_rank"] > 0
+    x = p.solve(dg.vector(f)).cpu().numpy()
+    err = rel(x, sig)
+    print("ifmm tiny eps 1e-6 error", err, st)
+    assert err < 1e-4
+
+
+def test_ifmm_no_far_field_is_exact(lib, tiny):
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    p = lib.IFMM(dg, eps=1e-3, cheb_n=4, max_depth=1)
+    x = p.solve(dg.vector(f)).cpu().numpy()
+    assert rel(x, sig) < 1e-10
+
+
+@pytest.mark.parametrize("n,eps,bound", [(6, 1e-3, 5e-2), (10, 1e-6, 1e-4), (14, 1e-9, 1e-6)])
+def test_ifmm_error_follows_eps(lib, tiny, n, eps, bound):
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    x = lib.IFMM(dg, eps=eps, cheb_n=n).solve(dg.vector(f)).cpu().numpy()
+    assert rel(x, sig) < bound
+
+
+def test_ifmm_fp32(lib, tiny):
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    x = lib.IFMM(dg, eps=1e-3, cheb_n=6, precision=1).solve(dg.vector(f)).cpu().numpy()
+    assert rel(x, sig) < 5e-2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_with_ifmm_matches_lu(lib, tiny, precision):
+    """Mixed precision: an FP32 IFMM inside FP64 FGMRES still reaches the
+    FP64 solution, because the preconditioned directions are kept in FP64."""
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    p = lib.IFMM(dg, eps=1e-3, cheb_n=6, precision=precision)
+    r = lib.gmres(dg, dg.vector(f), pc=p, tol=1e-12)
+    assert r.status == 0
+    x = r.sigma.cpu().numpy()
+    assert np.linalg.norm(f - a @ x) / np.linalg.norm(f) < 1e-12
+    assert rel(x, sig) < 1e-8
+    ref = solve.fgmres(lambda v: a @ v, f, precond=ifmm.IFMM(g, eps=1e-3, cheb_n=6, dense=a),
+                       tol=1e-12)
+    assert r.iters <= ref.iters + 3
+
+
+def test_ifmm_beats_block_diagonal_iterations(lib):
+    g = make_geometry(dict(length=10.0, n_ext=2048, n_pores=100, r_lo=0.02, r_hi=0.05,
+                           n_int=64, gap_pore=0.005, gap_wall=0.1), 3)
+    f = poiseuille_rhs(g)
+    dg = lib.DeviceGeometry(g)
+    r_bd = lib.gmres(dg, dg.vector(f), pc=lib.BlockDiagonal(dg), tol=1e-10)
+    r_if = lib.gmres(dg, dg.vector(f), pc=lib.IFMM(dg, eps=1e-3, cheb_n=6), tol=1e-10)
+    print("iterations bd", r_bd.iters, "ifmm", r_if.iters)
+    assert r_if.status == 0 and r_bd.status == 0
+    assert r_if.iters < r_bd.iters / 4
