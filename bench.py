@@ -40,8 +40,14 @@ def main():
     ap.add_argument("--pc", default="both", choices=["ifmm", "bd", "both"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
-    ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--ifmm-precision", type=int, default=1)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--cheb-n", type=int, default=8)
+    ap.add_argument("--ifmm-precision", type=int, default=1,
+                    help="0 = FP64 factor/apply, 1 = FP32 (mixed precision)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--matvec-only", type=int, default=0,
+                    help="time this many plain matvecs instead of solves (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=512)
     args = ap.parse_args()
@@ -65,10 +71,38 @@ def main():
     nn, n = g.n_nodes, g.n_unknowns
     log(f"[bench] workload {args.workload} seed {args.seed}: Nn={nn} n={n}")
 
+    if args.matvec_only:
+        x = dg.vector(np.random.default_rng(7).standard_normal(n))
+        y = lib.matvec(dg, x)
+        torch.cuda.synchronize()
+        lib.kernel_timing(True)
+        lib.kernel_time()
+        t0 = time.perf_counter()
+        for _ in range(args.matvec_only):
+            lib.matvec(dg, x, out=y)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        lib.kernel_timing(False)
+        kms, kc = lib.kernel_time()
+        if args.copy_calibration:
+            a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            a.fill_(1.0)
+            torch.cuda.synchronize()
+            b.copy_(a)
+            torch.cuda.synchronize()
+        k_ms = kms / max(kc, 1)
+        print(json.dumps({"matvecs": args.matvec_only, "ms_per_matvec": 1e3 * el / args.matvec_only,
+                          "pair_kernel_ms": k_ms,
+                          "pair_tflops": PAIR_FLOPS * float(nn) ** 2 / (k_ms * 1e-3) / 1e12,
+                          "frac_fp64_peak": PAIR_FLOPS * float(nn) ** 2 / (k_ms * 1e-3) / FP64_VECTOR_PEAK}),
+              flush=True)
+        return
+
     def make_pc(kind):
         if kind == "bd":
             return lib.BlockDiagonal(dg)
-        return lib.IFMM(dg, eps=args.eps, precision=args.ifmm_precision)
+        return lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=args.ifmm_precision)
 
     kinds = ["ifmm", "bd"] if args.pc == "both" else [args.pc]
     results = {}
@@ -89,11 +123,15 @@ def main():
         torch.cuda.synchronize()
         lib.kernel_timing(True)
         lib.kernel_time()
-        iters, relres, relpc, tmv, tpc, tar = [], [], [], [], [], []
+        iters, relres, relpc, tmv, tpc, tar, tfac = [], [], [], [], [], [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
+            tf0 = time.perf_counter()
             pc = make_pc(kind)
+            torch.cuda.synchronize()
+            tfac.append(time.perf_counter() - tf0)
             r = lib.gmres(dg, fd, pc=pc, tol=args.tol, max_iter=args.max_iter)
+            stats = pc.stats() if kind == "ifmm" else None
             pc.close()
             iters.append(r.iters)
             relres.append(r.rel_res_true)
@@ -111,9 +149,21 @@ def main():
             iters=iters, rel_res_true=max(relres), rel_res_pc=max(relpc),
             converged=all(x <= args.tol for x in relres),
             t_matvec_s=float(np.mean(tmv)), t_precond_apply_s=float(np.mean(tpc)),
-            t_arnoldi_s=float(np.mean(tar)),
+            t_arnoldi_s=float(np.mean(tar)), t_factor_s=float(np.mean(tfac)),
+            ifmm_stats=stats,
             pair_kernel_ms=kms / max(kcount, 1), pair_kernel_launches=kcount)
         log(f"[bench] {kind}: {results[kind]}")
+
+    if args.copy_calibration:
+        # one plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # give the scale of the HBM counters on this device
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB read + 1 GiB written")
 
     if not results:
         print("no preconditioner could be built", file=sys.stderr)
@@ -176,7 +226,9 @@ def main():
         "config": {"workload": f"{args.workload}: pipe [0,50]x[0,1], 4096 wall nodes, "
                                f"1000 pores x 64 nodes, Poiseuille inflow",
                    "seed": args.seed, "n_unknowns": n, "pc": head, "tol": args.tol,
-                   "ifmm_eps": args.eps if head == "ifmm" else None},
+                   "ifmm_eps": args.eps if head == "ifmm" else None,
+                   "ifmm_cheb_n": args.cheb_n if head == "ifmm" else None,
+                   "ifmm_precision": ("fp32" if args.ifmm_precision else "fp64") if head == "ifmm" else None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solves": results,

@@ -112,10 +112,14 @@ int stokes_bie_assemble(const sbie_geom *g, const int64_t *rows, int64_t nr,
  * with its smooth diagonal limit, sum_{j != i} w_j D(x_i, x_j, n_j) sigma_j
  * + w_i kappa_i/(2 pi) t t^T sigma_i, in the node rows and zero in the pore
  * rows (mode SBIE_MV_DLP_ONLY).  Section 2.1 (double-layer kernel), Section
- * 2.2 (discretisation).  x and y are device FP64 of length n and must not
+ * 2.2 (discretisation).  Mode SBIE_MV_FULL_ACCURATE computes the same y = A x
+ * with compensated (two-sum) accumulation of every sum, for residuals that
+ * must resolve much less than the rounding of the plain sums when the
+ * density is far larger than the data; it costs about 1.5 matvecs.
+ * x and y are device FP64 of length n and must not
  * overlap.  Direct O(Nn^2) evaluation; scratch memory comes from the
  * stream-ordered allocator and is released before return. */
-enum { SBIE_MV_FULL = 0, SBIE_MV_DLP_ONLY = 1 };
+enum { SBIE_MV_FULL = 0, SBIE_MV_DLP_ONLY = 1, SBIE_MV_FULL_ACCURATE = 2 };
 int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y, int mode,
                       void *stream);
 

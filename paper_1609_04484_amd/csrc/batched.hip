@@ -36,6 +36,9 @@ void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
 
 namespace {
 
+constexpr int kBlockedMin = 160;  // larger matrices use the blocked inverse
+constexpr int kPanel = 32;
+
 // ----------------------------------------------------------------------------
 // GEMM: one 64 x 64 output tile per workgroup, 256 threads, 4 x 4 per thread
 // ----------------------------------------------------------------------------
@@ -152,7 +155,12 @@ __global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__
   if (tid < d.rows) {
     const T v = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
     T *y = d.y + tid;
-    *y = d.beta != T(0) ? fma(d.beta, *y, v) : v;
+    if (d.beta != T(0)) {
+      const T base = d.y0 ? d.y0[tid] : *y;
+      *y = fma(d.beta, base, v);
+    } else {
+      *y = v;
+    }
   }
 }
 
@@ -167,8 +175,12 @@ __global__ __launch_bounds__(256) void copy_desc(const CopyDesc<T> *__restrict__
   const int c1 = c0 + 16 < d.cols ? c0 + 16 : d.cols;
   for (int c = c0; c < c1; ++c)
     for (int r = threadIdx.x; r < d.rows; r += blockDim.x) {
-      const T v = d.trans ? d.src[c + (size_t)r * d.lds] : d.src[r + (size_t)c * d.lds];
       T *p = d.dst + r + (size_t)c * d.ldd;
+      if (!d.acc && d.alpha == T(0)) {   // zero fill: the source is not read
+        *p = T(0);
+        continue;
+      }
+      const T v = d.trans ? d.src[c + (size_t)r * d.lds] : d.src[r + (size_t)c * d.lds];
       *p = d.acc ? fma(d.alpha, v, *p) : d.alpha * v;
     }
 }
@@ -402,6 +414,113 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
   if (tid == 0) *d.count = k;
 }
 
+
+// ----------------------------------------------------------------------------
+// Blocked Gauss-Jordan with partial pivoting, helper kernels.  For the panel
+// of columns [k0, k0 + pb) of every matrix: pivot rows are chosen by an LU
+// with partial pivoting of a copy of the tall panel (rows k0..n) -- the same
+// rows Gauss-Jordan with partial pivoting would choose -- and the row swaps
+// are applied to the whole matrix.
+// ----------------------------------------------------------------------------
+template <class T>
+struct PanelDesc {
+  T *A;          // n x n, ld n
+  T *work;       // (n - k0) x pb scratch
+  int *ipiv;     // n entries (global row chosen at step k)
+  int n, k0, pb;
+  int32_t *info;
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void panel_pivot_kernel(const PanelDesc<T> *__restrict__ descs) {
+  const PanelDesc<T> d = descs[blockIdx.x];
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const int tid = threadIdx.x;
+  const int h = d.n - d.k0;
+  T *W = d.work;
+  for (int c = 0; c < d.pb; ++c)
+    for (int r = tid; r < h; r += 256) W[r + (size_t)c * h] = d.A[(d.k0 + r) + (size_t)(d.k0 + c) * d.n];
+  __syncthreads();
+  for (int t = 0; t < d.pb; ++t) {
+    double best = -1.0;
+    int bi = t;
+    for (int r = t + tid; r < h; r += 256) {
+      const double v = fabs((double)W[r + (size_t)t * h]);
+      if (v > best) { best = v; bi = r; }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double ov = red_v[tid + st];
+        const int oi = red_i[tid + st];
+        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = ov;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const double pv = red_v[0];
+    const int p = red_i[0];
+    __syncthreads();
+    if (!(pv > 0.0) || !isfinite(pv)) {
+      if (tid == 0) *d.info = d.k0 + t + 1;
+      return;
+    }
+    if (tid == 0) d.ipiv[d.k0 + t] = d.k0 + p;
+    if (p != t)
+      for (int c = tid; c < d.pb; c += 256) {
+        const T a = W[t + (size_t)c * h];
+        W[t + (size_t)c * h] = W[p + (size_t)c * h];
+        W[p + (size_t)c * h] = a;
+      }
+    __syncthreads();
+    const T inv = T(1) / W[t + (size_t)t * h];
+    for (int r = t + 1 + tid; r < h; r += 256) W[r + (size_t)t * h] *= inv;
+    __syncthreads();
+    for (int r = t + 1 + tid; r < h; r += 256) {
+      const T l = W[r + (size_t)t * h];
+      for (int c = t + 1; c < d.pb; ++c) W[r + (size_t)c * h] = fma(-l, W[t + (size_t)c * h], W[r + (size_t)c * h]);
+    }
+    __syncthreads();
+  }
+  // apply the swaps to whole rows of A, in order
+  for (int t = 0; t < d.pb; ++t) {
+    const int k = d.k0 + t, p = d.ipiv[k];
+    if (p != k)
+      for (int c = tid; c < d.n; c += 256) {
+        const T a = d.A[k + (size_t)c * d.n];
+        d.A[k + (size_t)c * d.n] = d.A[p + (size_t)c * d.n];
+        d.A[p + (size_t)c * d.n] = a;
+      }
+    __syncthreads();
+  }
+}
+
+// Undo the row interchanges as column interchanges of the inverse.
+template <class T>
+__global__ __launch_bounds__(256) void unswap_columns_kernel(T *const *__restrict__ ptrs,
+                                                             const int *__restrict__ ns,
+                                                             int *const *__restrict__ ipivs) {
+  T *A = ptrs[blockIdx.x];
+  const int n = ns[blockIdx.x];
+  const int *ipiv = ipivs[blockIdx.x];
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = ipiv[k];
+    if (p != k)
+      for (int r = threadIdx.x; r < n; r += 256) {
+        const T a = A[r + (size_t)k * n];
+        A[r + (size_t)k * n] = A[r + (size_t)p * n];
+        A[r + (size_t)p * n] = a;
+      }
+    __syncthreads();
+  }
+}
+
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -510,6 +629,118 @@ void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
   SBIE_LAUNCH_CHECK();
 }
 
+
+template <class T>
+void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int> &ns,
+                             int32_t *info_dev, Stager &st, hipStream_t s) {
+  const int nm = (int)ptrs.size();
+  if (nm == 0) return;
+  std::vector<T *> sp, bp;
+  std::vector<int> sn, bn, sidx, bidx;
+  for (int i = 0; i < nm; ++i) {
+    if (ns[i] <= kBlockedMin) { sp.push_back(ptrs[i]); sn.push_back(ns[i]); sidx.push_back(i); }
+    else { bp.push_back(ptrs[i]); bn.push_back(ns[i]); bidx.push_back(i); }
+  }
+  const int nbm = (int)bp.size();
+  const int nb = kPanel;
+  int maxn = 0;
+  for (int n : bn) maxn = std::max(maxn, n);
+  const int npan = nbm ? (maxn + nb - 1) / nb : 0;
+  // status words: [small matrices | panel pivots per big matrix | tile
+  // inverses per (panel, active big matrix)]
+  DevBuf<int32_t> stat((size_t)sp.size() + nbm + (size_t)npan * std::max(1, nbm) + 1);
+  fill_value<int>((int *)stat.p, stat.n, 0, s);
+  int32_t *info_small = stat.p;
+  int32_t *info_panel = stat.p + sp.size();
+  int32_t *info_tile = info_panel + nbm;
+  if (!sp.empty()) inverse_batched<T>(sp, sn, info_small, st, s);
+  std::vector<std::vector<int>> active(npan);
+  DevBuf<T> work, C, R, P;
+  DevBuf<int> piv;
+  if (nbm) {
+    size_t ws = 0;
+    for (int n : bn) ws += (size_t)n * nb;
+    work.alloc(ws);
+    C.alloc(ws);
+    R.alloc(ws);
+    P.alloc((size_t)nbm * nb * nb);
+    piv.alloc((size_t)nbm * maxn);
+    std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm);
+    std::vector<int *> ipv(nbm);
+    size_t o = 0;
+    for (int b = 0; b < nbm; ++b) {
+      woff[b] = work.p + o;
+      coff[b] = C.p + o;
+      roff[b] = R.p + o;
+      o += (size_t)bn[b] * nb;
+      poff[b] = P.p + (size_t)b * nb * nb;
+      ipv[b] = piv.p + (size_t)b * maxn;
+    }
+    for (int it = 0; it < npan; ++it) {
+      const int k0 = it * nb;
+      std::vector<PanelDesc<T>> pd;
+      std::vector<T *> pp;
+      std::vector<int> pn;
+      std::vector<CopyDesc<T>> cP, cC, cZ, cRz, cRow, cPin;
+      std::vector<GemmDesc<T>> gR, gUpd, gCol;
+      for (int b = 0; b < nbm; ++b) {
+        const int n = bn[b];
+        if (k0 >= n) continue;
+        active[it].push_back(b);
+        const int pb = std::min(nb, n - k0);
+        T *A = bp[b];
+        pd.push_back({A, woff[b], ipv[b], n, k0, pb, info_panel + b});
+        pp.push_back(poff[b]);
+        pn.push_back(pb);
+        cP.push_back({A + k0 + (size_t)k0 * n, n, poff[b], pb, pb, pb, 0, 0, T(1)});
+        cC.push_back({A + (size_t)k0 * n, n, coff[b], n, n, pb, 0, 0, T(1)});
+        cZ.push_back({nullptr, 1, coff[b] + k0, n, pb, pb, 0, 0, T(0)});
+        gR.push_back({pb, n, pb, 0, 0, poff[b], pb, A + k0, n, roff[b], pb, T(1), T(0)});
+        cRz.push_back({nullptr, 1, roff[b] + (size_t)k0 * pb, pb, pb, pb, 0, 0, T(0)});
+        gUpd.push_back({n, n, pb, 0, 0, coff[b], n, roff[b], pb, A, n, T(-1), T(1)});
+        cRow.push_back({roff[b], pb, A + k0, n, pb, n, 0, 0, T(1)});
+        gCol.push_back({n, pb, pb, 0, 0, coff[b], n, poff[b], pb, A + (size_t)k0 * n, n, T(-1), T(0)});
+        cPin.push_back({poff[b], pb, A + k0 + (size_t)k0 * n, n, pb, pb, 0, 0, T(1)});
+      }
+      if (pd.empty()) break;
+      auto *dd = (const PanelDesc<T> *)st.put(pd.data(), pd.size() * sizeof(PanelDesc<T>), s);
+      panel_pivot_kernel<T><<<(unsigned)pd.size(), 256, 0, s>>>(dd);   // choose rows, swap
+      SBIE_LAUNCH_CHECK();
+      copy_batched<T>(cP, st, s);                                      // P = A_pp
+      inverse_batched<T>(pp, pn, info_tile + (size_t)it * nbm, st, s);  // P = A_pp^-1
+      copy_batched<T>(cC, st, s);                                      // C = A[:, p]
+      copy_batched<T>(cZ, st, s);                                      // C[p, :] = 0
+      gemm_batched<T>(gR, st, s);                                      // R = P A[p, :]
+      copy_batched<T>(cRz, st, s);                                     // R[:, p] = 0
+      gemm_batched<T>(gUpd, st, s);                                    // A -= C R
+      copy_batched<T>(cRow, st, s);                                    // A[p, :] = R
+      gemm_batched<T>(gCol, st, s);                                    // A[:, p] = -C P
+      copy_batched<T>(cPin, st, s);                                    // A_pp = P
+    }
+    auto *pd_ = (T *const *)st.put(bp.data(), bp.size() * sizeof(T *), s);
+    auto *nd_ = (const int *)st.put(bn.data(), bn.size() * sizeof(int), s);
+    auto *id_ = (int *const *)st.put(ipv.data(), ipv.size() * sizeof(int *), s);
+    unswap_columns_kernel<T><<<nbm, 256, 0, s>>>(pd_, nd_, id_);
+    SBIE_LAUNCH_CHECK();
+  }
+  // collect the statuses (the scratch buffers are released at scope exit,
+  // so the stream must drain first anyway)
+  std::vector<int32_t> hs(stat.n, 0);
+  SBIE_HIP(hipMemcpyAsync(hs.data(), stat.p, stat.n * 4, hipMemcpyDeviceToHost, s));
+  SBIE_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> out(nm, 0);
+  for (size_t q = 0; q < sidx.size(); ++q) out[sidx[q]] = hs[q];
+  for (int b = 0; b < nbm; ++b)
+    if (hs[sp.size() + b] != 0) out[bidx[b]] = hs[sp.size() + b];
+  for (int it = 0; it < npan; ++it)
+    for (size_t q = 0; q < active[it].size(); ++q) {
+      const int32_t v = hs[sp.size() + nbm + (size_t)it * nbm + q];
+      if (v != 0 && out[bidx[active[it][q]]] == 0) out[bidx[active[it][q]]] = it * nb + v;
+    }
+  SBIE_HIP(hipMemcpyAsync(info_dev, out.data(), nm * 4, hipMemcpyHostToDevice, s));
+  SBIE_HIP(hipStreamSynchronize(s));
+}
+
 template <class T>
 void norms_batched(const std::vector<NormDesc<T>> &d, double *out_dev, Stager &st,
                    hipStream_t s) {
@@ -573,6 +804,9 @@ void convert(const A *src, B *dst, size_t n, hipStream_t s) {
   template void copy_launch<T>(const CopyDesc<T> *, int, int, hipStream_t);              \
   template void inverse_batched<T>(const std::vector<T *> &, const std::vector<int> &,   \
                                    int32_t *, Stager &, hipStream_t);                    \
+  template void inverse_batched_blocked<T>(const std::vector<T *> &,                     \
+                                           const std::vector<int> &, int32_t *, Stager &, \
+                                           hipStream_t);                                 \
   template void norms_batched<T>(const std::vector<NormDesc<T>> &, double *, Stager &,   \
                                  hipStream_t);                                           \
   template void normalize_columns<T>(T *, int, int, int, hipStream_t);                   \

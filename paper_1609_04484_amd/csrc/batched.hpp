@@ -29,10 +29,11 @@ struct GemvTerm {
   T alpha;
 };
 
-// y (rows) = beta y + sum of terms [t0, t0 + nt)
+// y (rows) = beta y0 + sum of terms [t0, t0 + nt), with y0 = y when null
 template <class T>
 struct GemvDesc {
   T *y;
+  const T *y0;
   int rows;
   int t0, nt;
   T beta;
@@ -85,6 +86,13 @@ void copy_launch(const CopyDesc<T> *d, int nd, int max_rows, hipStream_t s);
 template <class T>
 void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                      int32_t *info_dev, Stager &st, hipStream_t s);
+
+// Same, with matrices larger than a threshold inverted by blocked
+// Gauss-Jordan with partial pivoting whose rank-nb updates are batched GEMMs
+// (spread over all compute units); synchronises the stream.
+template <class T>
+void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int> &ns,
+                             int32_t *info_dev, Stager &st, hipStream_t s);
 
 // Frobenius norms of blocks (rows x cols, ld) into out[b] (double).
 template <class T>

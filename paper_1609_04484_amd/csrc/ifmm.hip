@@ -22,6 +22,8 @@
 // with device-resident GEMV descriptor lists prepared once per factorisation.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
+#include <string>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -419,28 +421,57 @@ auto &blk(M &map, int a, int b) {
   return it->second;
 }
 
+// One colour phase of the application: a forward and a backward launch.
+//   forward:  t_i = A_xx g_i;  (z-rhs of the parent) = A_zx g_i;
+//             rhs_j -= N_ji g_i with N_ji = S_ji A_xx   (j active neighbour)
+//   backward: x_i = t_i - sum_k M_ik x_k + A_xy y_i with M_ik = A_xx S_ik
 template <class T>
 struct SolvePhase {
-  // device descriptor arrays
-  CopyDesc<T> *save = nullptr;
-  int nsave = 0, save_cols = 1;
-  GemvDesc<T> *f1 = nullptr;
-  GemvTerm<T> *f1t = nullptr;
-  int nf1 = 0;
-  GemvDesc<T> *f2 = nullptr;
-  GemvTerm<T> *f2t = nullptr;
-  int nf2 = 0;
-  CopyDesc<T> *restore = nullptr;
-  int nrestore = 0;
-  GemvDesc<T> *b1 = nullptr;
-  GemvTerm<T> *b1t = nullptr;
-  int nb1 = 0;
-  GemvDesc<T> *b2 = nullptr;
-  GemvTerm<T> *b2t = nullptr;
-  int nb2 = 0;
+  GemvDesc<T> *f = nullptr;
+  GemvTerm<T> *ft = nullptr;
+  int nf = 0;
+  GemvDesc<T> *b = nullptr;
+  GemvTerm<T> *bt = nullptr;
+  int nb = 0;
 };
 
 }  // namespace
+
+// Stage timers of the factorisation, printed when SBIE_VERBOSE is set (each
+// stage boundary then synchronises the stream, so timings are exclusive).
+struct StageClock {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::chrono::steady_clock::time_point last;
+  std::map<std::string, double> acc;
+  explicit StageClock(hipStream_t st) : on(std::getenv("SBIE_VERBOSE") != nullptr), s(st) {
+    last = std::chrono::steady_clock::now();
+  }
+  void tick(const char *name, int level = -1) {
+    if (!on) return;
+    if (level >= 0) {
+      char buf[64];
+      std::snprintf(buf, sizeof(buf), "%s_L%d", name, level);
+      tick_s(buf);
+      return;
+    }
+    tick_s(name);
+  }
+  void tick_s(const std::string &name) {
+    (void)hipStreamSynchronize(s);
+    const auto now = std::chrono::steady_clock::now();
+    acc[name] += std::chrono::duration<double>(now - last).count();
+    last = now;
+  }
+  ~StageClock() {
+    if (!on) return;
+    double tot = 0.0;
+    for (auto &kv : acc) tot += kv.second;
+    std::fprintf(stderr, "[ifmm] factor stages (s):");
+    for (auto &kv : acc) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
+    std::fprintf(stderr, " total=%.4f\n", tot);
+  }
+};
 
 struct IfmmImplBase {
   virtual ~IfmmImplBase() = default;
@@ -464,26 +495,47 @@ struct IfmmImpl : IfmmImplBase {
   GemvTerm<T> *root_t = nullptr;
   int root_nd = 0;
 
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
+  ~IfmmImpl() override {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+
+  // Capture the fixed launch sequence of one application (everything between
+  // the gather of b and the scatter of x) into a HIP graph.
+  void build_graph() {
+    if (std::getenv("SBIE_NO_GRAPH")) return;
+    SBIE_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    SBIE_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    run_sweeps(cap_stream);
+    SBIE_HIP(hipStreamEndCapture(cap_stream, &graph));
+    SBIE_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+  }
+
   void apply(const double *b, double *x, hipStream_t s) const override {
     const int64_t nd = n_leaf_dofs;
     gather_rhs<T><<<ceil_div(nd, 256), 256, 0, s>>>(leaf_dofs_all.p, nd, b, rhs[0]);
     SBIE_LAUNCH_CHECK();
-    const int nl = (int)phases.size();
-    for (int l = 0; l < nl; ++l)
-      for (const auto &ph : phases[l]) {
-        copy_launch<T>(ph.save, ph.nsave, 1, s);
-        gemv_launch<T>(ph.f1, ph.f1t, ph.nf1, 64, s);
-        gemv_launch<T>(ph.f2, ph.f2t, ph.nf2, 64, s);
-      }
-    gemv_launch<T>(root_d, root_t, root_nd, 64, s);
-    for (int l = nl - 1; l >= 0; --l)
-      for (auto it = phases[l].rbegin(); it != phases[l].rend(); ++it) {
-        copy_launch<T>(it->restore, it->nrestore, 1, s);
-        gemv_launch<T>(it->b1, it->b1t, it->nb1, 64, s);
-        gemv_launch<T>(it->b2, it->b2t, it->nb2, 64, s);
-      }
+    if (graph_exec)
+      SBIE_HIP(hipGraphLaunch(graph_exec, s));
+    else
+      run_sweeps(s);
     scatter_sol<T><<<ceil_div(nd, 256), 256, 0, s>>>(leaf_dofs_all.p, nd, xbuf[0], x);
     SBIE_LAUNCH_CHECK();
+  }
+
+  void run_sweeps(hipStream_t s) const {
+    const int nl = (int)phases.size();
+    for (int l = 0; l < nl; ++l)
+      for (const auto &ph : phases[l]) gemv_launch<T>(ph.f, ph.ft, ph.nf, 64, s);
+    gemv_launch<T>(root_d, root_t, root_nd, 64, s);
+    for (int l = nl - 1; l >= 0; --l)
+      for (auto it = phases[l].rbegin(); it != phases[l].rend(); ++it)
+        gemv_launch<T>(it->b, it->bt, it->nb, 64, s);
   }
 
   template <class D>
@@ -496,10 +548,11 @@ struct IfmmImpl : IfmmImplBase {
 
   // split a y-block of `rows` rows into <= 64-row GEMV descriptors
   static void add_gemv(std::vector<GemvDesc<T>> &ds, std::vector<GemvTerm<T>> &ts, T *y, int rows,
-                       T beta, const std::vector<GemvTerm<T>> &terms) {
+                       T beta, const std::vector<GemvTerm<T>> &terms, const T *y0 = nullptr) {
     for (int r0 = 0; r0 < rows; r0 += 64) {
       GemvDesc<T> d;
       d.y = y + r0;
+      d.y0 = y0 ? y0 + r0 : nullptr;
       d.rows = std::min(64, rows - r0);
       d.t0 = (int)ts.size();
       d.beta = beta;
@@ -538,7 +591,9 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     SBIE_HIP(hipMemcpy(py.data() + nn, g->cy, m_p * 8, hipMemcpyDeviceToHost));
     SBIE_HIP(hipMemcpy(rad.data(), g->radius, m_p * 8, hipMemcpyDeviceToHost));
   }
+  StageClock clk(s);
   HTree tr = build_tree(px, py, nn, g->curve_off[m_p], leaf_target, prm->max_depth);
+  clk.tick("tree");
   const double leaf_h = tr.lv[tr.depth].h;
   for (int k = 0; k < m_p; ++k)
     if (rad[k] >= leaf_h)
@@ -578,7 +633,8 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   // per-level state containers
   std::vector<int> m(nleaf);
   for (int b = 0; b < nleaf; ++b) m[b] = (int)tr.leaf_dofs[b].size();
-  std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> S;  // persistent blocks
+  std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> S;  // near field of the level
+  auto level_arena = std::make_unique<Arena>((size_t)256 << 20);
   // leaf near field
   {
     std::vector<AsmDesc> ad;
@@ -586,7 +642,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     for (int b = 0; b < nleaf; ++b)
       for (int c : leaf.nbrs[b]) {
         Blk<T> bl;
-        bl.p = persist.get<T>((size_t)m[b] * m[c]);
+        bl.p = level_arena->get<T>((size_t)m[b] * m[c]);
         bl.ld = m[b];
         S.emplace(std::make_pair(b, c), bl);
         AsmDesc a;
@@ -606,8 +662,8 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       SBIE_LAUNCH_CHECK();
     }
   }
+  clk.tick("leaf_assemble");
   // leaf Chebyshev rows
-  auto level_arena = std::make_unique<Arena>((size_t)256 << 20);
   std::vector<T *> phi(nleaf), psi(nleaf), gvec(nleaf), hvec(nleaf);
   {
     std::vector<ChebBox> cb(nleaf);
@@ -704,6 +760,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       gemm_batched<T>(gd, st, s);
     }
 
+    clk.tick("kernel_tables");
     // ---- initial bases W_b = orth([Phi U_K, Psi V_K, g, h])
     std::vector<T *> W(nb), phiU(nb), psiV(nb);
     std::vector<int> r(nb);
@@ -738,6 +795,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       st.reset();
       r = hr;
     }
+    clk.tick("initial_bases");
     // ---- projections and initial couplings
     std::vector<T *> Gh(nb), Hh(nb), g0(nb), h0(nb);
     std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> Tc;
@@ -809,6 +867,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       st.reset();
     }
 
+    clk.tick("initial_couplings");
     // ---- elimination, colour by colour
     std::vector<char> gone(nb, 0);
     std::vector<std::vector<int>> colors(9);
@@ -822,6 +881,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       std::vector<int> act;
       T *axx, *axy, *azx;
       int r;
+      std::vector<T *> mik, nji;   // per active neighbour
     };
     std::vector<Rec> recs;
     std::vector<std::vector<int>> phase_boxes;
@@ -850,7 +910,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         ns.push_back(m[i]);
       }
       copy_batched<T>(cd, st, s);
-      inverse_batched<T>(sinv, ns, info.p, st, s);
+      inverse_batched_blocked<T>(sinv, ns, info.p, st, s);
       // B: X = S^{-1} W, Y = S^{-T} W ; C: Piv = W^T X
       std::vector<GemmDesc<T>> gd;
       for (int e = 0; e < ne; ++e) {
@@ -874,7 +934,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         pivn.push_back(r[i]);
       }
       gemm_batched<T>(gd, st, s);
-      inverse_batched<T>(pivp, pivn, info.p + ne, st, s);
+      inverse_batched_blocked<T>(pivp, pivn, info.p + ne, st, s);
       // D: A_xy = X Piv^{-1}, A_zx = Piv^{-1} Y^T, A_xx = S^{-1} - A_xy Y^T
       gd.clear();
       for (int e = 0; e < ne; ++e) {
@@ -893,13 +953,15 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
       gemm_batched<T>(gd, st, s);
       // E: M_ik = A_xx S_ik, G_ik = A_zx S_ik, B_ij = S_ji A_xy
-      std::vector<std::unordered_map<int, T *>> Mik(ne), Gik(ne), Bij(ne);
+      std::vector<std::unordered_map<int, T *>> Mik(ne), Gik(ne), Bij(ne), Nji(ne);
       gd.clear();
       for (int e = 0; e < ne; ++e) {
         const int i = E[e];
         const int ri = std::max(1, r[i]);
         for (int k : act[e]) {
-          T *mm = pa.get<T>((size_t)m[i] * m[k]);
+          T *mm = persist.get<T>((size_t)m[i] * m[k]);
+          T *nn_ = persist.get<T>((size_t)m[k] * m[i]);
+          Nji[e][k] = nn_;
           T *gg = pa.get<T>((size_t)ri * m[k]);
           T *bb = pa.get<T>((size_t)m[k] * ri);
           Mik[e][k] = mm;
@@ -909,9 +971,11 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
           gd.push_back({m[i], m[k], m[i], 0, 0, sinv[e], m[i], sik.p, sik.ld, mm, m[i], T(1), T(0)});
           gd.push_back({r[i], m[k], m[i], 0, 0, azx[e], ri, sik.p, sik.ld, gg, ri, T(1), T(0)});
           gd.push_back({m[k], r[i], m[i], 0, 0, ski.p, ski.ld, axy[e], m[i], bb, m[k], T(1), T(0)});
+          gd.push_back({m[k], m[i], m[i], 0, 0, ski.p, ski.ld, sinv[e], m[i], nn_, m[k], T(1), T(0)});
         }
       }
       gemm_batched<T>(gd, st, s);
+      clk.tick("elim_pivots", lev);
       // F: fill-ins
       struct Far {
         int e, j, k;
@@ -1021,6 +1085,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
       copy_batched<T>(cc, st, s);
       gemm_batched<T>(gd, st, s);
+      clk.tick("elim_fillins");
       //   project out the current basis twice: P = W^T C, C -= W P
       for (int pass = 0; pass < 2; ++pass) {
         std::vector<GemmDesc<T>> g1, g2;
@@ -1051,6 +1116,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       st.reset();
       std::vector<int> rold = r;
       for (size_t a = 0; a < aug.size(); ++a) r[aug[a].j] += add[a];
+      clk.tick("elim_recompress", lev);
       // H: couplings with the new bases
       std::vector<CopyDesc<T>> tc;
       std::vector<GemmDesc<T>> g1, g2;
@@ -1080,12 +1146,18 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       gemm_batched<T>(g2, st, s);
       // record
       for (int e = 0; e < ne; ++e) {
-        recs.push_back({E[e], act[e], sinv[e], axy[e], azx[e], r[E[e]]});
+        Rec rc{E[e], act[e], sinv[e], axy[e], azx[e], r[E[e]], {}, {}};
+        for (int k : act[e]) {
+          rc.mik.push_back(Mik[e][k]);
+          rc.nji.push_back(Nji[e][k]);
+        }
+        recs.push_back(rc);
         gone[E[e]] = 1;
       }
       SBIE_HIP(hipStreamSynchronize(s));
       st.reset();
       (void)rold;
+      clk.tick("elim_couplings");
     }
     for (int b = 0; b < nb; ++b) max_rank = std::max(max_rank, r[b]);
 
@@ -1108,7 +1180,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       size_t tot = 0;
       for (int p = 0; p < np_; ++p)
         for (int q : P.nbrs[p]) tot += (size_t)std::max(1, mp[p]) * std::max(1, mp[q]);
-      T *pool = persist.get<T>(tot);
+      T *pool = next_arena->get<T>(tot);
       fill_value<T>(pool, tot, T(0), s);
       size_t used = 0;
       for (int p = 0; p < np_; ++p)
@@ -1155,6 +1227,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       gemm_batched<T>(g1, st, s);
       gemm_batched<T>(g2, st, s);
     }
+    clk.tick("level_change");
     // ---- solve plan of this level (parent offsets now known)
     {
       T *prhs = rhs[li + 1];
@@ -1164,48 +1237,38 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       std::vector<SolvePhase<T>> &plist = phases[li];
       for (const auto &E : phase_boxes) {
         SolvePhase<T> ph;
-        std::vector<CopyDesc<T>> save, restore;
-        std::vector<GemvDesc<T>> f1, f2, b1, b2;
-        std::vector<GemvTerm<T>> f1t, f2t, b1t, b2t;
+        std::vector<GemvDesc<T>> fd, bd;
+        std::vector<GemvTerm<T>> ft, bt;
         for (int i : E) {
           const Rec &rc = *byi[i];
           const int mi = m[i], ri = rc.r;
           T *gi = lrhs + off[i];
-          save.push_back({gi, mi, lgs + off[i], mi, mi, 1, 0, 0, T(1)});
-          restore.push_back({lgs + off[i], mi, lv + off[i], mi, mi, 1, 0, 0, T(1)});
-          add_gemv(f1, f1t, lt + off[i], mi, T(0), {GemvTerm<T>{rc.axx, gi, mi, mi, 0, T(1)}});
           const int pp = L.parent[i];
+          add_gemv(fd, ft, lt + off[i], mi, T(0), {GemvTerm<T>{rc.axx, gi, mi, mi, 0, T(1)}});
           if (ri > 0)
-            add_gemv(f1, f1t, prhs + poff[pp] + in_par[i], ri, T(0),
+            add_gemv(fd, ft, prhs + poff[pp] + in_par[i], ri, T(0),
                      {GemvTerm<T>{rc.azx, gi, std::max(1, ri), mi, 0, T(1)}});
-          for (int j : rc.act) {
-            const Blk<T> &sji = blk(S, j, i);
-            add_gemv(f2, f2t, lrhs + off[j], m[j], T(1), {GemvTerm<T>{sji.p, lt + off[i], sji.ld, mi, 0, T(-1)}});
+          for (size_t q = 0; q < rc.act.size(); ++q) {
+            const int j = rc.act[q];
+            add_gemv(fd, ft, lrhs + off[j], m[j], T(1), {GemvTerm<T>{rc.nji[q], gi, m[j], mi, 0, T(-1)}});
           }
           std::vector<GemvTerm<T>> terms;
-          for (int k : rc.act) {
-            const Blk<T> &sik = blk(S, i, k);
-            terms.push_back({sik.p, lx + off[k], sik.ld, m[k], 0, T(-1)});
+          for (size_t q = 0; q < rc.act.size(); ++q) {
+            const int k = rc.act[q];
+            terms.push_back({rc.mik[q], lx + off[k], mi, m[k], 0, T(-1)});
           }
-          if (!terms.empty()) add_gemv(b1, b1t, lv + off[i], mi, T(1), terms);
-          std::vector<GemvTerm<T>> t2 = {GemvTerm<T>{rc.axx, lv + off[i], mi, mi, 0, T(1)}};
-          if (ri > 0) t2.push_back({rc.axy, px_ + poff[pp] + in_par[i], mi, ri, 0, T(1)});
-          add_gemv(b2, b2t, lx + off[i], mi, T(0), t2);
+          if (ri > 0) terms.push_back({rc.axy, px_ + poff[pp] + in_par[i], mi, ri, 0, T(1)});
+          add_gemv(bd, bt, lx + off[i], mi, T(1), terms, lt + off[i]);
         }
-        ph.save = upload(save);
-        ph.nsave = (int)save.size();
-        ph.restore = upload(restore);
-        ph.nrestore = (int)restore.size();
-        ph.f1 = upload(f1); ph.f1t = upload(f1t); ph.nf1 = (int)f1.size();
-        ph.f2 = upload(f2); ph.f2t = upload(f2t); ph.nf2 = (int)f2.size();
-        ph.b1 = upload(b1); ph.b1t = upload(b1t); ph.nb1 = (int)b1.size();
-        ph.b2 = upload(b2); ph.b2t = upload(b2t); ph.nb2 = (int)b2.size();
+        ph.f = upload(fd); ph.ft = upload(ft); ph.nf = (int)fd.size();
+        ph.b = upload(bd); ph.bt = upload(bt); ph.nb = (int)bd.size();
         plist.push_back(ph);
       }
     }
     SBIE_HIP(hipStreamSynchronize(s));
     st.reset();
     // advance
+    clk.tick("solve_plan");
     S = std::move(Sp);
     phi = nphi;
     psi = npsi;
@@ -1233,7 +1296,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
     copy_batched<T>(cd, st, s);
     if (root_dim > 0) {
-      inverse_batched<T>({root_inv}, {root_dim}, info.p, st, s);
+      inverse_batched_blocked<T>({root_inv}, {root_dim}, info.p, st, s);
       int32_t hi = 0;
       SBIE_HIP(hipMemcpyAsync(&hi, info.p, 4, hipMemcpyDeviceToHost, s));
       SBIE_HIP(hipStreamSynchronize(s));
@@ -1247,7 +1310,10 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     }
   }
   SBIE_HIP(hipStreamSynchronize(s));
+  clk.tick("root");
   level_arena.reset();
+  build_graph();
+  clk.tick("graph");
   stats.levels = tr.depth + 1;
   stats.leaves = nleaf;
   stats.max_rank = max_rank;

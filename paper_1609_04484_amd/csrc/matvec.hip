@@ -89,6 +89,17 @@ __global__ void wall_flux(int64_t wall_start, int64_t nn,
   }
 }
 
+// s + c += x with the rounding error of the addition carried in c (Knuth's
+// two-sum): used by the compensated mode, whose residuals must resolve
+// 1e-10 of the data when the density is much larger than the data.
+__device__ __forceinline__ void two_sum_acc(double &s, double &c, double x) {
+#pragma clang fp contract(off)
+  const double t = s + x;
+  const double bp = t - s;
+  c += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
 // 1/d to full FP64 precision: hardware reciprocal estimate refined by one
 // third-order Newton step, r' = r (1 + e + e^2) with e = 1 - d r.
 __device__ __forceinline__ double recip(double d) {
@@ -97,13 +108,13 @@ __device__ __forceinline__ double recip(double d) {
   return fma(r, fma(e, e, e), r);
 }
 
-template <int T>
+template <int T, bool ACC>
 __global__ __launch_bounds__(kBlock) void dlp_pairs(
     const double *__restrict__ src, const double *__restrict__ xs,
     const double *__restrict__ ys, int64_t nn, int64_t chunk,
     double *__restrict__ part) {
   const int64_t tile0 = (int64_t)blockIdx.x * (kBlock * T) + threadIdx.x;
-  double xi[T], yi[T], ax[T], ay[T];
+  double xi[T], yi[T], ax[T], ay[T], cxa[T], cya[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     int64_t i = tile0 + (int64_t)t * kBlock;
@@ -112,6 +123,8 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
     yi[t] = ys[i];
     ax[t] = 0.0;
     ay[t] = 0.0;
+    cxa[t] = 0.0;
+    cya[t] = 0.0;
   }
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < nn ? j0 + chunk : nn;
@@ -130,24 +143,33 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
       const double dn = fma(ry, say, rx * sax);
       const double ds = fma(ry, ssy, rx * ssx);
       const double c = (dn * ds) * (inv * inv);
-      ax[t] = fma(c, rx, ax[t]);
-      ay[t] = fma(c, ry, ay[t]);
+      if (ACC) {
+        two_sum_acc(ax[t], cxa[t], c * rx);
+        two_sum_acc(ay[t], cya[t], c * ry);
+      } else {
+        ax[t] = fma(c, rx, ax[t]);
+        ay[t] = fma(c, ry, ay[t]);
+      }
     }
   }
-  double *px = part + (int64_t)blockIdx.y * 2 * nn;
-  double *py = px + nn;
+  double *px = part + (int64_t)blockIdx.y * 4 * nn;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int64_t i = tile0 + (int64_t)t * kBlock;
     if (i < nn) {
       px[i] = ax[t];
-      py[i] = ay[t];
+      px[nn + i] = ay[t];
+      if (ACC) {
+        px[2 * nn + i] = cxa[t];
+        px[3 * nn + i] = cya[t];
+      }
     }
   }
 }
 
 // Stokeslet + rotlet columns: sum over pores of S(x_i - c_k) lambda_k
 // + r_k R(x_i - c_k) mu_k, without the 1/(4 pi) (applied in the epilogue).
+template <bool ACC>
 __global__ __launch_bounds__(kBlock) void completion_pairs(
     const double *__restrict__ psrc, const double *__restrict__ xs,
     const double *__restrict__ ys, int64_t nn, int m,
@@ -155,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void completion_pairs(
   const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = i0 < nn ? i0 : nn - 1;
   const double xi = xs[i], yi = ys[i];
-  double ax = 0.0, ay = 0.0;
+  double ax = 0.0, ay = 0.0, cxa = 0.0, cya = 0.0;
   const int k0 = blockIdx.y * kPoreChunk;
   const int k1 = k0 + kPoreChunk < m ? k0 + kPoreChunk : m;
   for (int k = k0; k < k1; ++k) {
@@ -166,18 +188,29 @@ __global__ __launch_bounds__(kBlock) void completion_pairs(
     const double inv = 1.0 / q2;
     const double lg = 0.5 * log(q2);
     const double dot = fma(qy, ly, qx * lx) * inv;
-    ax += -lg * lx + qx * dot + rmu * qy * inv;
-    ay += -lg * ly + qy * dot - rmu * qx * inv;
+    const double tx = -lg * lx + qx * dot + rmu * qy * inv;
+    const double ty = -lg * ly + qy * dot - rmu * qx * inv;
+    if (ACC) {
+      two_sum_acc(ax, cxa, tx);
+      two_sum_acc(ay, cya, ty);
+    } else {
+      ax += tx;
+      ay += ty;
+    }
   }
   if (i0 < nn) {
-    double *px = part + (int64_t)blockIdx.y * 2 * nn;
+    double *px = part + (int64_t)blockIdx.y * 4 * nn;
     px[i0] = ax;
     px[nn + i0] = ay;
+    if (ACC) {
+      px[2 * nn + i0] = cxa;
+      px[3 * nn + i0] = cya;
+    }
   }
 }
 
 __global__ void epilogue(int64_t nn, int64_t wall_start, int nchunks,
-                         int npchunks, int full,
+                         int npchunks, int full, int acc,
                          const double *__restrict__ part,
                          const double *__restrict__ nx,
                          const double *__restrict__ ny,
@@ -188,32 +221,51 @@ __global__ void epilogue(int64_t nn, int64_t wall_start, int nchunks,
                          double *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
-  double vx = 0.0, vy = 0.0;
+  // (value, error) pairs; the error parts are only used in the compensated
+  // mode, where every addition below is a two-sum
+  double vx = 0.0, vy = 0.0, ex = 0.0, ey = 0.0;
+  auto add = [&](double &v, double &e, double a) {
+    if (acc) two_sum_acc(v, e, a); else v += a;
+  };
   for (int c = 0; c < nchunks; ++c) {
-    vx += part[(int64_t)c * 2 * nn + i];
-    vy += part[(int64_t)c * 2 * nn + nn + i];
+    const double *p = part + (int64_t)c * 4 * nn;
+    add(vx, ex, p[i]);
+    add(vy, ey, p[nn + i]);
+    if (acc) {
+      ex += p[2 * nn + i];
+      ey += p[3 * nn + i];
+    }
   }
   const double sx = u[i], sy = u[nn + i];
   const double tx = -ny[i], ty = nx[i];
   const double d = w[i] * kappa[i] * (0.5 / kPi) * (tx * sx + ty * sy);
-  vx += d * tx;
-  vy += d * ty;
+  add(vx, ex, d * tx);
+  add(vy, ey, d * ty);
   if (full) {
-    double cx = 0.0, cy = 0.0;
+    double cx = 0.0, cy = 0.0, ecx = 0.0, ecy = 0.0;
     for (int c = 0; c < npchunks; ++c) {
-      cx += part[(int64_t)(nchunks + c) * 2 * nn + i];
-      cy += part[(int64_t)(nchunks + c) * 2 * nn + nn + i];
+      const double *p = part + (int64_t)(nchunks + c) * 4 * nn;
+      add(cx, ecx, p[i]);
+      add(cy, ecy, p[nn + i]);
+      if (acc) {
+        ecx += p[2 * nn + i];
+        ecy += p[3 * nn + i];
+      }
     }
-    vx += cx * (0.25 / kPi) - 0.5 * sx;
-    vy += cy * (0.25 / kPi) - 0.5 * sy;
+    add(vx, ex, cx * (0.25 / kPi));
+    add(vx, ex, ecx * (0.25 / kPi));
+    add(vy, ey, cy * (0.25 / kPi));
+    add(vy, ey, ecy * (0.25 / kPi));
+    add(vx, ex, -0.5 * sx);
+    add(vy, ey, -0.5 * sy);
     if (i >= wall_start) {
       const double f = scal[0] / scal[1];
-      vx += nx[i] * f;
-      vy += ny[i] * f;
+      add(vx, ex, nx[i] * f);
+      add(vy, ey, ny[i] * f);
     }
   }
-  out[i] = vx;
-  out[nn + i] = vy;
+  out[i] = vx + ex;
+  out[nn + i] = vy + ey;
 }
 
 // One wave per pore: the constraint rows lambda_k and mu_k.
@@ -298,7 +350,7 @@ MatvecWork plan_matvec(const sbie_geom *g) {
 size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g) {
   const int64_t nn = g->n_nodes;
   return (size_t)8 * nn + (size_t)8 * (g->n_pores + 1) +
-         (size_t)(w.chunks + w.pchunks) * 2 * nn + 8;
+         (size_t)(w.chunks + w.pchunks) * 4 * nn + 8;
 }
 
 void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
@@ -306,14 +358,15 @@ void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
   w.src = base;
   w.psrc = w.src + 8 * nn;
   w.part = w.psrc + 8 * (g->n_pores + 1);
-  w.scal = w.part + (size_t)(w.chunks + w.pchunks) * 2 * nn;
+  w.scal = w.part + (size_t)(w.chunks + w.pchunks) * 4 * nn;
 }
 
 void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
                 MatvecWork &w, hipStream_t s) {
   const int64_t nn = g->n_nodes;
   const int m = g->n_pores;
-  const int full = mode == SBIE_MV_FULL;
+  const int full = mode == SBIE_MV_FULL || mode == SBIE_MV_FULL_ACCURATE;
+  const bool acc = mode == SBIE_MV_FULL_ACCURATE;
   const int64_t wall_start = g->curve_off[m];
   const int64_t packn = nn > m ? nn : m;
   pack_sources<<<ceil_div(packn, 256), 256, 0, s>>>(
@@ -332,12 +385,17 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_HIP(hipEventCreate(&ev1));
     SBIE_HIP(hipEventRecord(ev0, s));
   }
-  switch (w.tpt) {
-    case 1: dlp_pairs<1><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-    case 2: dlp_pairs<2><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-    case 4: dlp_pairs<4><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-    case 8: dlp_pairs<8><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-    default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
+  if (acc) {
+    dlp_pairs<1, true><<<dim3(ceil_div(nn, kBlock), w.chunks), kBlock, 0, s>>>(
+        w.src, g->x, g->y, nn, chunk, w.part);
+  } else {
+    switch (w.tpt) {
+      case 1: dlp_pairs<1, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
+      case 2: dlp_pairs<2, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
+      case 4: dlp_pairs<4, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
+      case 8: dlp_pairs<8, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
+      default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
+    }
   }
   SBIE_LAUNCH_CHECK();
   if (g_timing) {
@@ -346,12 +404,16 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
   }
   if (full && m > 0) {
     dim3 pg(ceil_div(nn, kBlock), w.pchunks);
-    completion_pairs<<<pg, kBlock, 0, s>>>(w.psrc, g->x, g->y, nn, m,
-                                           w.part + (size_t)w.chunks * 2 * nn);
+    if (acc)
+      completion_pairs<true><<<pg, kBlock, 0, s>>>(w.psrc, g->x, g->y, nn, m,
+                                                   w.part + (size_t)w.chunks * 4 * nn);
+    else
+      completion_pairs<false><<<pg, kBlock, 0, s>>>(w.psrc, g->x, g->y, nn, m,
+                                                    w.part + (size_t)w.chunks * 4 * nn);
     SBIE_LAUNCH_CHECK();
   }
   epilogue<<<ceil_div(nn, 256), 256, 0, s>>>(nn, wall_start, w.chunks,
-                                             full ? w.pchunks : 0, full, w.part,
+                                             full ? w.pchunks : 0, full, acc ? 1 : 0, w.part,
                                              g->nx, g->ny, g->w, g->kappa, x,
                                              w.scal, y);
   SBIE_LAUNCH_CHECK();
@@ -375,7 +437,7 @@ extern "C" int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y,
   return sbie::guarded([&]() {
     sbie::validate_geom(g);
     if (!x || !y) sbie::fail(SBIE_INVALID_ARGUMENT, "null vector");
-    if (mode != SBIE_MV_FULL && mode != SBIE_MV_DLP_ONLY)
+    if (mode != SBIE_MV_FULL && mode != SBIE_MV_DLP_ONLY && mode != SBIE_MV_FULL_ACCURATE)
       sbie::fail(SBIE_INVALID_ARGUMENT, "unknown matvec mode %d", mode);
     const int64_t n = sbie::n_unknowns(g);
     if (x < y + n && y < x + n)

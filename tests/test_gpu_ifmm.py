@@ -100,3 +100,20 @@ def test_ifmm_beats_block_diagonal_iterations(lib):
     print("iterations bd", r_bd.iters, "ifmm", r_if.iters)
     assert r_if.status == 0 and r_bd.status == 0
     assert r_if.iters < r_bd.iters / 4
+
+
+def test_ifmm_graph_replay_matches_eager(lib, tiny, monkeypatch):
+    """The captured application replays identically, call after call, and
+    equals the eagerly launched sequence."""
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    p_graph = lib.IFMM(dg, eps=1e-6, cheb_n=10)
+    monkeypatch.setenv("SBIE_NO_GRAPH", "1")
+    p_eager = lib.IFMM(dg, eps=1e-6, cheb_n=10)
+    fd = dg.vector(f)
+    ref = p_eager.solve(fd).cpu().numpy()
+    for k in range(3):
+        v = random_vector(g.n_unknowns, 40 + k)
+        lib.matvec(dg, dg.vector(v))          # unrelated device work in between
+        x = p_graph.solve(fd).cpu().numpy()
+        assert np.array_equal(x, ref)
