@@ -36,7 +36,7 @@ void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
 
 namespace {
 
-constexpr int kBlockedMin = 160;  // larger matrices use the blocked inverse
+constexpr int kBlockedMin = 48;  // larger matrices use the blocked inverse
 constexpr int kPanel = 32;
 
 // ----------------------------------------------------------------------------
@@ -395,6 +395,9 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
     __syncthreads();
     ++k;
     for (int j = wv; j < d.c; j += 4) {
+      // a column already below the tolerance can never be chosen again and
+      // its residual norm only decreases: leave it alone
+      if (!(norms[j] > tol2)) continue;
       T *col = d.R + (size_t)j * d.ldr;
       double dt = 0.0;
       for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);

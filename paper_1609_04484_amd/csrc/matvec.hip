@@ -108,6 +108,33 @@ __device__ __forceinline__ double recip(double d) {
   return fma(r, fma(e, e, e), r);
 }
 
+// Reciprocals of T positive numbers with one hardware reciprocal: the
+// product of all of them is inverted (and refined) once, and each 1/d_t is
+// recovered as that inverse times the product of the others (Montgomery's
+// batch-inversion trick).  The d_t are squared distances between nodes, so
+// their product stays far inside the FP64 range.
+template <int T>
+__device__ __forceinline__ void batch_recip(const double *d, double *out) {
+  if (T == 1) {
+    out[0] = recip(d[0]);
+  } else if (T == 2) {
+    const double r = recip(d[0] * d[1]);
+    out[0] = r * d[1];
+    out[1] = r * d[0];
+  } else if (T == 4) {
+    const double p01 = d[0] * d[1], p23 = d[2] * d[3];
+    const double r = recip(p01 * p23);
+    const double r01 = r * p23, r23 = r * p01;
+    out[0] = r01 * d[1];
+    out[1] = r01 * d[0];
+    out[2] = r23 * d[3];
+    out[3] = r23 * d[2];
+  } else {
+#pragma unroll
+    for (int h = 0; h < T; h += 4) batch_recip<4>(d + h, out + h);
+  }
+}
+
 template <int T, bool ACC>
 __global__ __launch_bounds__(kBlock) void dlp_pairs(
     const double *__restrict__ src, const double *__restrict__ xs,
@@ -117,38 +144,46 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
   double xi[T], yi[T], ax[T], ay[T], cxa[T], cya[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    int64_t i = tile0 + (int64_t)t * kBlock;
-    i = i < nn ? i : nn - 1;
-    xi[t] = xs[i];
-    yi[t] = ys[i];
+    const int64_t i = tile0 + (int64_t)t * kBlock;
+    // padding targets of the last tile sit far away from every node and at
+    // distinct places, so at most one target per thread can coincide with a
+    // source (the batched reciprocal multiplies the squared distances)
+    xi[t] = i < nn ? xs[i] : xs[nn - 1] + 1.0e3 * (double)(t + 1);
+    yi[t] = i < nn ? ys[i] : ys[nn - 1];
     ax[t] = 0.0;
     ay[t] = 0.0;
     cxa[t] = 0.0;
     cya[t] = 0.0;
   }
-  const int64_t j0 = (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = j0 + chunk < nn ? j0 + chunk : nn;
+  // uniform loop bounds kept in scalar registers
+  const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * chunk));
+  int64_t j1 = j0 + chunk < nn ? j0 + chunk : nn;
+  j1 = __builtin_amdgcn_readfirstlane((int)j1);
   for (int64_t j = j0; j < j1; ++j) {
     const double *s = src + 8 * j;  // wave-uniform: scalar loads
     const double sx = s[0], sy = s[1], sax = s[2], say = s[3], ssx = s[4],
                  ssy = s[5];
+    double rx[T], ry[T], r2[T], inv[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const double rx = xi[t] - sx;
-      const double ry = yi[t] - sy;
+      rx[t] = xi[t] - sx;
+      ry[t] = yi[t] - sy;
       // the self pair has r = 0 exactly: clamping rho^2 keeps 1/rho^4 finite
       // and the pair's factors (r.a)(r.sigma) are exactly zero
-      const double r2 = fmax(fma(ry, ry, rx * rx), 1e-100);
-      const double inv = recip(r2);
-      const double dn = fma(ry, say, rx * sax);
-      const double ds = fma(ry, ssy, rx * ssx);
-      const double c = (dn * ds) * (inv * inv);
+      r2[t] = fmax(fma(ry[t], ry[t], rx[t] * rx[t]), 1e-100);
+    }
+    batch_recip<T>(r2, inv);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const double dn = fma(ry[t], say, rx[t] * sax);
+      const double ds = fma(ry[t], ssy, rx[t] * ssx);
+      const double c = (dn * ds) * (inv[t] * inv[t]);
       if (ACC) {
-        two_sum_acc(ax[t], cxa[t], c * rx);
-        two_sum_acc(ay[t], cya[t], c * ry);
+        two_sum_acc(ax[t], cxa[t], c * rx[t]);
+        two_sum_acc(ay[t], cya[t], c * ry[t]);
       } else {
-        ax[t] = fma(c, rx, ax[t]);
-        ay[t] = fma(c, ry, ay[t]);
+        ax[t] = fma(c, rx[t], ax[t]);
+        ay[t] = fma(c, ry[t], ay[t]);
       }
     }
   }

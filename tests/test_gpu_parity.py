@@ -215,7 +215,9 @@ def test_gmres_exact_start_and_cap(lib, tiny):
     ref = solve.fgmres(lambda v: a @ v, f, tol=1e-10, restart=60, max_iter=600)
     assert ref.converged
     assert r.status == 0 and r.rel_res_true < 1e-10
-    assert abs(r.iters - ref.iters) <= 5
+    # the device cycles aim at tol/2 before the compensated true-residual
+    # check, so they may run a few iterations longer than the oracle's
+    assert abs(r.iters - ref.iters) <= max(5, 0.1 * ref.iters)
     # short restarts stagnate on this system on both sides
     r = lib.gmres(dg, dg.vector(f), tol=1e-10, restart=15, max_iter=300)
     ref = solve.fgmres(lambda v: a @ v, f, tol=1e-10, restart=15, max_iter=300)
