@@ -125,10 +125,20 @@ __global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__
   for (int t = d.t0; t < d.t0 + d.nt; ++t) {
     const GemvTerm<T> tm = terms[t];
     if (!tm.trans) {
-      T s = T(0);
-      if (lane < d.rows)
-        for (int c = wv; c < tm.cols; c += 4) s = fma(tm.A[lane + (size_t)c * tm.lda], tm.x[c], s);
-      acc = fma(tm.alpha, s, acc);
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+      if (lane < d.rows) {
+        const T *a = tm.A + lane;
+        int c = wv;
+        // four independent chains keep several loads in flight
+        for (; c + 12 < tm.cols; c += 16) {
+          s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
+          s1 = fma(a[(size_t)(c + 4) * tm.lda], tm.x[c + 4], s1);
+          s2 = fma(a[(size_t)(c + 8) * tm.lda], tm.x[c + 8], s2);
+          s3 = fma(a[(size_t)(c + 12) * tm.lda], tm.x[c + 12], s3);
+        }
+        for (; c < tm.cols; c += 4) s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
+      }
+      acc = fma(tm.alpha, (s0 + s1) + (s2 + s3), acc);
     } else {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -296,6 +306,87 @@ __global__ __launch_bounds__(256) void gj_kernel(T *const *__restrict__ ptrs,
       }
     __syncthreads();
   }
+  if (tid == 0) info[b] = 0;
+}
+
+
+// Gauss-Jordan with partial pivoting for n <= 64 with the matrix held in LDS
+// (one workgroup per matrix); same contract as gj_kernel.
+template <class T>
+__global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ ptrs,
+                                                       const int *__restrict__ ns,
+                                                       int32_t *__restrict__ info) {
+  __shared__ T M[64][65];
+  __shared__ T rowk[64], fcol[64];
+  __shared__ int ipiv[64];
+  __shared__ double red_v[64];
+  __shared__ int red_i[64];
+  const int b = blockIdx.x;
+  const int n = ns[b];
+  T *A = ptrs[b];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += 256) M[e % n][e / n] = A[e];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      if (tid >= k && tid < n) { best = fabs((double)M[tid][k]); bi = tid; }
+      red_v[tid] = best;
+      red_i[tid] = bi;
+    }
+    __syncthreads();
+    for (int st = 32; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double ov = red_v[tid + st];
+        const int oi = red_i[tid + st];
+        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = ov;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const double pv = red_v[0];
+    const int p = red_i[0];
+    if (!(pv > 0.0) || !isfinite(pv)) {
+      if (tid == 0) info[b] = k + 1;
+      return;
+    }
+    if (tid == 0) ipiv[k] = p;
+    if (p != k && tid < n) {
+      const T t = M[k][tid];
+      M[k][tid] = M[p][tid];
+      M[p][tid] = t;
+    }
+    __syncthreads();
+    const T invd = T(1) / M[k][k];
+    if (tid < n) {
+      rowk[tid] = (tid == k ? T(1) : M[k][tid]) * invd;
+      fcol[tid] = tid == k ? T(0) : M[tid][k];
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      if (i == k) {
+        M[i][j] = rowk[j];
+      } else {
+        const T a = j == k ? T(0) : M[i][j];
+        M[i][j] = fma(-fcol[i], rowk[j], a);
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = ipiv[k];
+    if (p != k && tid < n) {
+      const T t = M[tid][k];
+      M[tid][k] = M[tid][p];
+      M[tid][p] = t;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += 256) A[e] = M[e % n][e / n];
   if (tid == 0) info[b] = 0;
 }
 
@@ -628,7 +719,10 @@ void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
   if (shmem > 56 * 1024) fail(SBIE_UNSUPPORTED, "dense block of size %d too large to invert", mx);
   auto *pd = (T *const *)st.put(ptrs.data(), ptrs.size() * sizeof(T *), s);
   auto *nd = (const int *)st.put(ns.data(), ns.size() * sizeof(int), s);
-  gj_kernel<T><<<(unsigned)ptrs.size(), 256, shmem, s>>>(pd, nd, info_dev);
+  if (mx <= 64)
+    gj_small_kernel<T><<<(unsigned)ptrs.size(), 256, 0, s>>>(pd, nd, info_dev);
+  else
+    gj_kernel<T><<<(unsigned)ptrs.size(), 256, shmem, s>>>(pd, nd, info_dev);
   SBIE_LAUNCH_CHECK();
 }
 

@@ -38,6 +38,7 @@ namespace {
 
 constexpr int kSketch = 48;   // Gaussian sketch width per far fill-in block
 constexpr int kKernelSketch = 128;
+constexpr int kPgsSketch = 192;   // sketch width of wide recompression candidates
 
 // ---------------------------------------------------------------------------
 // Device arena: bump allocation from large chunks, freed together
@@ -1100,13 +1101,35 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         gemm_batched<T>(g1, st, s);
         gemm_batched<T>(g2, st, s);
       }
+      //   wide candidate sets are sketched by a Gaussian matrix first: the
+      //   range of C Omega is the range of C with high probability when the
+      //   rank found stays well below the sketch width
+      int cmax = 0;
+      for (const auto &ag : aug) cmax = std::max(cmax, ag.c);
+      std::vector<GemmDesc<T>> gsk;
+      std::vector<T *> ysk(aug.size(), nullptr);
+      if (cmax > kPgsSketch) {
+        T *om = pa.get<T>((size_t)cmax * kPgsSketch);
+        gaussian_fill<T>(om, (size_t)cmax * kPgsSketch, 5000 + 131 * lev + col, s);
+        for (size_t a = 0; a < aug.size(); ++a) {
+          if (aug[a].c <= kPgsSketch) continue;
+          const int j = aug[a].j;
+          ysk[a] = pa.get<T>((size_t)m[j] * kPgsSketch);
+          gsk.push_back({m[j], kPgsSketch, aug[a].c, 0, 0, aug[a].cand, m[j], om, cmax, ysk[a], m[j],
+                         T(1.0 / std::sqrt((double)kPgsSketch)), T(0)});
+        }
+        gemm_batched<T>(gsk, st, s);
+      }
       std::vector<PgsDesc<T>> pd;
       for (size_t a = 0; a < aug.size(); ++a) {
         const int j = aug[a].j;
         if (aug[a].c == 0) {
           continue;
         }
-        pd.push_back({aug[a].cand, m[j], m[j], aug[a].c, W[j], m[j], r[j], m[j], eps, counts.p + a});
+        if (ysk[a])
+          pd.push_back({ysk[a], m[j], m[j], kPgsSketch, W[j], m[j], r[j], m[j], eps, counts.p + a});
+        else
+          pd.push_back({aug[a].cand, m[j], m[j], aug[a].c, W[j], m[j], r[j], m[j], eps, counts.p + a});
       }
       fill_value<int>(counts.p, aug.size() + 1, 0, s);
       pgs_batched<T>(pd, st, s);
