@@ -218,6 +218,72 @@ typedef struct {
 int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
                 const gmres_params *p, gmres_result *res, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper: an initial guess for GMRES,
+ * which stays the judge of the solution).  A per-pore multilayer perceptron
+ * (FP32, exact-erf GELU between layers, none after the last) maps 64
+ * geometry features of a pore to 64 Fourier coefficients of the density on
+ * that pore.  Activations are column-major (width x batch).
+ * ------------------------------------------------------------------------ */
+typedef struct sbie_mlp sbie_mlp;
+/* widths (host): nlayers + 1 layer widths.  Weights are He-normal from a
+ * counter-based generator seeded by `seed`; biases zero. */
+int mlp_create(int nlayers, const int32_t *widths, uint64_t seed, sbie_mlp **out,
+               void *stream);
+int mlp_destroy(sbie_mlp *net);
+int mlp_num_params(const sbie_mlp *net, int64_t *count);
+/* Parameters as one FP32 device array: for each layer, W (out x in,
+ * column-major) then b (out). */
+int mlp_get_params(const sbie_mlp *net, float *dst, void *stream);
+int mlp_set_params(sbie_mlp *net, const float *src, void *stream);
+/* Y (out x batch) = network(X (in x batch)). */
+int mlp_forward(sbie_mlp *net, const float *X, int32_t batch, float *Y, void *stream);
+/* Mean squared error against the standardised T and its gradient (kept for mlp_adam_step and
+ * copied to grad when non-null; device, num_params floats); *loss (host,
+ * optional) receives the loss; synchronises when loss is requested. */
+int mlp_loss_grad(sbie_mlp *net, const float *X, const float *T, int32_t batch,
+                  float *grad, double *loss, void *stream);
+/* Standardisation (device FP32 arrays): the network sees
+ * (x - in_mean) * in_scale and predicts targets standardised as
+ * (t - out_mean) / out_std; mlp_forward returns de-standardised outputs and
+ * mlp_loss_grad's loss is the MSE of the standardised targets.  Defaults are
+ * the identity.  mlp_fit_scaling sets them from the mean and standard
+ * deviation of every row of X and T (a row with zero spread keeps scale 1). */
+int mlp_set_scaling(sbie_mlp *net, const float *in_mean, const float *in_scale,
+                    const float *out_mean, const float *out_std, void *stream);
+int mlp_get_scaling(const sbie_mlp *net, float *in_mean, float *in_scale, float *out_mean,
+                    float *out_std, void *stream);
+int mlp_fit_scaling(sbie_mlp *net, const float *X, const float *T, int32_t batch, void *stream);
+/* One Adam step with bias correction using the last gradient. */
+int mlp_adam_step(sbie_mlp *net, float lr, float beta1, float beta2, float eps,
+                  void *stream);
+/* Features of every pore (64 x M floats, device): radius; offsets and radii
+ * of the 16 nearest pores (ties by index, zero padded); the inflow profile
+ * k (H^2 - y_c^2) with k = 1/H^2 for the channel [y_lo, y_hi] and its slope at
+ * the centre height; the distances to the two walls; zeros to 64. */
+int warmstart_features(const sbie_geom *g, double y_lo, double y_hi, float *feats,
+                       void *stream);
+/* Fourier coefficients of a density on every pore (64 x M floats): per
+ * velocity component a_0, a_1..a_15, b_1..b_15, a_16 with angles measured at
+ * the pore centre (discrete Fourier transform of the nodal values). */
+int warmstart_labels(const sbie_geom *g, const double *sigma, float *coeffs, void *stream);
+/* Initial guess x0 (device FP64, length n): the Fourier series on every pore,
+ * the given wall density (2 * N_ext values: x then y components; NULL = 0) on
+ * the wall, and lambda, mu from the constraint functionals of x0. */
+int warmstart_assemble(const sbie_geom *g, const float *coeffs, const double *wall_sigma,
+                       double *x0, void *stream);
+
+/* Improve an initial guess x0 (device FP64, length n) in place with two
+ * steps that cannot raise the residual of the second: (1) solve the wall rows
+ * exactly for the wall density with every other unknown held fixed,
+ * x0_wall += A_ww^{-1} (f - A x0)_wall, where wall_bd is the block-diagonal
+ * preconditioner of the same pipe without pores (its one block is A_ww, which
+ * depends only on the wall); (2) scale x0 by alpha = <f, A x0> / <A x0, A x0>,
+ * the minimiser of ||f - alpha A x0||.  *alpha (host, optional) receives the
+ * factor; synchronises when it is requested.  Two matrix-vector products. */
+int warmstart_refine(const sbie_geom *g, const sbie_bd *wall_bd, const double *f, double *x0,
+                     double *alpha, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

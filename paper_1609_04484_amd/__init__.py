@@ -1,6 +1,7 @@
 """MI355X-native solver for the completed double-layer Stokes system of a
 pipe filled with circular pores: HIP kernels behind a C ABI
 (``include/stokes_ifmm.h``) and this thin Python binding."""
-from ._lib import (BlockDiagonal, DeviceGeometry, IFMM, SbieError, SolveResult,  # noqa: F401
+from ._lib import (MLP, BlockDiagonal, DeviceGeometry, IFMM, SbieError, SolveResult,  # noqa: F401
                    assemble, gmres, kernel_time, kernel_timing, load, matvec,
-                   set_matvec_shape)
+                   set_matvec_shape, warmstart_assemble, warmstart_features,
+                   warmstart_labels, warmstart_refine)

@@ -101,6 +101,26 @@ EXPORTS = {
     "ifmm_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(IfmmStats)]),
     "gmres_solve": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp,
                                    ctypes.POINTER(GmresParams), ctypes.POINTER(GmresResult), _c_dp]),
+    "mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
+                                  ctypes.POINTER(ctypes.c_void_p), _c_dp]),
+    "mlp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "mlp_num_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp]),
+    "mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp]),
+    "mlp_forward": (ctypes.c_int, [ctypes.c_void_p, _c_dp, ctypes.c_int32, _c_dp, _c_dp]),
+    "mlp_loss_grad": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, ctypes.c_int32, _c_dp,
+                                     ctypes.POINTER(ctypes.c_double), _c_dp]),
+    "warmstart_refine": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_void_p, _c_dp, _c_dp,
+                                        ctypes.POINTER(ctypes.c_double), _c_dp]),
+    "mlp_set_scaling": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
+    "mlp_get_scaling": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
+    "mlp_fit_scaling": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, ctypes.c_int32, _c_dp]),
+    "mlp_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, _c_dp]),
+    "warmstart_features": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_double, ctypes.c_double,
+                                          _c_dp, _c_dp]),
+    "warmstart_labels": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp]),
+    "warmstart_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp, _c_dp]),
 }
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARGUMENT", -2: "INVALID_GEOMETRY",
@@ -297,3 +317,105 @@ def gmres(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000
                              ctypes.byref(r), _stream(stream)))
     return SolveResult(sigma, r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
                        r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, hist[:r.iters + 1].copy())
+
+
+class MLP:
+    """The warm-start network (device parameters, hand-written kernels)."""
+
+    def __init__(self, widths=(64, 256, 256, 256, 64), seed=0, stream=None):
+        self.widths = list(widths)
+        w = (ctypes.c_int32 * len(widths))(*widths)
+        h = ctypes.c_void_p()
+        check(load().mlp_create(len(widths) - 1, w, seed, ctypes.byref(h), _stream(stream)))
+        self.h = h
+        n = ctypes.c_int64()
+        check(load().mlp_num_params(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def params(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(load().mlp_get_params(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def set_params(self, p: torch.Tensor, stream=None):
+        p = p.to(device="cuda", dtype=torch.float32).contiguous()
+        check(load().mlp_set_params(self.h, _ptr(p), _stream(stream)))
+
+    def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        """X: (batch, in) float32 row-major == (in x batch) column-major."""
+        X = X.contiguous()
+        Y = torch.empty((X.shape[0], self.widths[-1]), dtype=torch.float32, device=X.device)
+        check(load().mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y), _stream(stream)))
+        return Y
+
+    def loss_grad(self, X: torch.Tensor, T: torch.Tensor, want_grad=False, stream=None):
+        X, T = X.contiguous(), T.contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device) if want_grad else None
+        loss = ctypes.c_double()
+        check(load().mlp_loss_grad(self.h, _ptr(X), _ptr(T), X.shape[0],
+                                   _ptr(g) if g is not None else None, ctypes.byref(loss),
+                                   _stream(stream)))
+        return loss.value, g
+
+    def scaling(self, stream=None):
+        """(in_mean, in_scale, out_mean, out_std) as device tensors."""
+        a = [torch.empty(w, dtype=torch.float32, device="cuda")
+             for w in (self.widths[0], self.widths[0], self.widths[-1], self.widths[-1])]
+        check(load().mlp_get_scaling(self.h, *[_ptr(t) for t in a], _stream(stream)))
+        return tuple(a)
+
+    def set_scaling(self, in_mean, in_scale, out_mean, out_std, stream=None):
+        a = [t.to(device="cuda", dtype=torch.float32).contiguous()
+             for t in (in_mean, in_scale, out_mean, out_std)]
+        check(load().mlp_set_scaling(self.h, *[_ptr(t) for t in a], _stream(stream)))
+
+    def fit_scaling(self, X: torch.Tensor, T: torch.Tensor, stream=None):
+        X, T = X.contiguous(), T.contiguous()
+        check(load().mlp_fit_scaling(self.h, _ptr(X), _ptr(T), X.shape[0], _stream(stream)))
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        check(load().mlp_adam_step(self.h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            load().mlp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def warmstart_features(dg: DeviceGeometry, y_lo=0.0, y_hi=1.0, stream=None) -> torch.Tensor:
+    m = dg.geom.n_pores
+    out = torch.zeros((max(m, 1), 64), dtype=torch.float32, device="cuda")
+    check(load().warmstart_features(ctypes.byref(dg.c), y_lo, y_hi, _ptr(out), _stream(stream)))
+    return out[:m]
+
+
+def warmstart_labels(dg: DeviceGeometry, sigma: torch.Tensor, stream=None) -> torch.Tensor:
+    m = dg.geom.n_pores
+    out = torch.zeros((max(m, 1), 64), dtype=torch.float32, device="cuda")
+    check(load().warmstart_labels(ctypes.byref(dg.c), _ptr(sigma), _ptr(out), _stream(stream)))
+    return out[:m]
+
+
+def warmstart_assemble(dg: DeviceGeometry, coeffs: torch.Tensor, wall_sigma=None,
+                       stream=None) -> torch.Tensor:
+    x0 = torch.empty(dg.n, dtype=torch.float64, device="cuda")
+    c = coeffs.contiguous() if coeffs.numel() else torch.zeros(64, dtype=torch.float32, device="cuda")
+    check(load().warmstart_assemble(ctypes.byref(dg.c), _ptr(c),
+                                    _ptr(wall_sigma) if wall_sigma is not None else None,
+                                    _ptr(x0), _stream(stream)))
+    return x0
+
+
+def warmstart_refine(dg: DeviceGeometry, wall_bd, f: torch.Tensor, x0: torch.Tensor,
+                     stream=None) -> float:
+    """Wall solve and minimal-residual scaling of x0 in place; returns alpha."""
+    alpha = ctypes.c_double()
+    check(load().warmstart_refine(ctypes.byref(dg.c), wall_bd.h, _ptr(f), _ptr(x0),
+                                  ctypes.byref(alpha), _stream(stream)))
+    return alpha.value

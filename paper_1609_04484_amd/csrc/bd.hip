@@ -86,6 +86,8 @@ void bd_build(const sbie_geom *g, sbie_bd *bd, hipStream_t s) {
   bd->factor_bytes = (mo + bd->nwall * bd->nwall) * 8;
 }
 
+int64_t bd_size(const sbie_bd *bd) { return bd->n; }
+
 void bd_apply(const sbie_bd *bd, const double *b, double *x, hipStream_t s) {
   block_gemv(bd->mats.p, bd->moff.p, bd->idx.p, bd->ioff.p, bd->sz.p, bd->nsmall,
              bd->max_small, b, x, s);

@@ -6,6 +6,7 @@
 namespace sbie {
 
 void bd_apply(const sbie_bd *bd, const double *b, double *x, hipStream_t s);
+int64_t bd_size(const sbie_bd *bd);
 void ifmm_apply(const ifmm_handle *h, const double *b, double *x, hipStream_t s);
 
 inline void precond_apply(const gmres_params *p, const double *in, double *out,
