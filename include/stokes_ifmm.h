@@ -219,6 +219,46 @@ int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
                 const gmres_params *p, gmres_result *res, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batches of independent geometries.
+ * ------------------------------------------------------------------------ */
+/* y_b = A_b x_b for every member b (geoms: host array of `count`
+ * descriptors; x, y: host arrays of device pointers).  Every stage of the
+ * product is one launch for the whole batch; same modes and results as
+ * stokes_dlp_matvec with the same launch shape.  Synchronises the stream. */
+int stokes_dlp_matvec_batched(const sbie_geom *geoms, int32_t count, const double *const *x,
+                              double *const *y, int mode, void *stream);
+
+/* Per-member preconditioner of a batched solve (pc as in gmres_params). */
+typedef struct {
+  int32_t pc;
+  int32_t use_x0;
+  const sbie_bd *bd;
+  const ifmm_handle *ifmm;
+} gmres_member;
+
+/* The FGMRES of gmres_solve for every member, advanced in lockstep: one
+ * batched matvec and one set of batched Gram-Schmidt launches per step for
+ * all members still iterating, one host copy of all Hessenberg columns per
+ * step; preconditioners applied member by member.  f, sigma: host arrays of
+ * device pointers.  restart <= 0 means unrestarted.  results[b] as for
+ * gmres_solve, except that t_total_s is the whole batch's time, t_arnoldi_s
+ * the time of all lockstep steps (preconditioners, products and
+ * Gram-Schmidt together) and t_matvec_s = t_precond_s = 0.  Returns
+ * SBIE_NOT_CONVERGED when any member did not converge (see results). */
+int gmres_solve_batched(const sbie_geom *geoms, int32_t count, const double *const *f,
+                        double *const *sigma, const gmres_member *members, double tol,
+                        int32_t max_iter, int32_t restart, gmres_result *results, void *stream);
+
+/* IFMM factorisations of every member (out: host array of `count` handles),
+ * run concurrently by `workers` host threads, each on a stream of its own
+ * (the factorisation is latency bound: small launches with host
+ * synchronisation between elimination phases, so several members overlap on
+ * the device).  On error every handle created is destroyed and out[] is set
+ * to NULL.  Synchronises. */
+int ifmm_factor_batched(const sbie_geom *geoms, int32_t count, const ifmm_params *params,
+                        ifmm_handle **out, int32_t workers);
+
+/* ------------------------------------------------------------------------
  * Learned warm start (not part of the paper: an initial guess for GMRES,
  * which stays the judge of the solution).  A per-pore multilayer perceptron
  * (FP32, exact-erf GELU between layers, none after the last) maps 64

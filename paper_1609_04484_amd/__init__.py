@@ -2,6 +2,7 @@
 pipe filled with circular pores: HIP kernels behind a C ABI
 (``include/stokes_ifmm.h``) and this thin Python binding."""
 from ._lib import (MLP, BlockDiagonal, DeviceGeometry, IFMM, SbieError, SolveResult,  # noqa: F401
-                   assemble, gmres, kernel_time, kernel_timing, load, matvec,
-                   set_matvec_shape, warmstart_assemble, warmstart_features,
-                   warmstart_labels, warmstart_refine)
+                   assemble, gmres, gmres_batched, ifmm_factor_batched, kernel_time,
+                   kernel_timing, load, matvec, matvec_batched, set_matvec_shape,
+                   warmstart_assemble, warmstart_features, warmstart_labels,
+                   warmstart_refine)

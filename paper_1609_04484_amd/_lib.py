@@ -83,6 +83,15 @@ class GmresResult(ctypes.Structure):
     ]
 
 
+class GmresMember(ctypes.Structure):
+    _fields_ = [
+        ("pc", ctypes.c_int32),
+        ("use_x0", ctypes.c_int32),
+        ("bd", ctypes.c_void_p),
+        ("ifmm", ctypes.c_void_p),
+    ]
+
+
 EXPORTS = {
     "sbie_last_error": (ctypes.c_char_p, []),
     "stokes_bie_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, ctypes.c_int64,
@@ -101,6 +110,18 @@ EXPORTS = {
     "ifmm_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(IfmmStats)]),
     "gmres_solve": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp,
                                    ctypes.POINTER(GmresParams), ctypes.POINTER(GmresResult), _c_dp]),
+    "stokes_dlp_matvec_batched": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _c_dp]),
+    "gmres_solve_batched": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(GmresMember), ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(GmresResult), _c_dp]),
+    "ifmm_factor_batched": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_int32,
+                                           ctypes.POINTER(IfmmParams),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
     "mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
                                   ctypes.POINTER(ctypes.c_void_p), _c_dp]),
     "mlp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -256,8 +277,11 @@ class BlockDiagonal:
 
 class IFMM:
     def __init__(self, dg: DeviceGeometry, eps=1e-6, cheb_n=10, leaf_target=64,
-                 max_depth=0, precision=0, stream=None):
+                 max_depth=0, precision=0, stream=None, handle=None):
         self.dg = dg
+        if handle is not None:          # adopt a handle made by ifmm_factor_batched
+            self.h = handle
+            return
         p = IfmmParams(eps=eps, cheb_n=cheb_n, leaf_target=leaf_target,
                        max_depth=max_depth, precision=precision)
         h = ctypes.c_void_p()
@@ -419,3 +443,54 @@ def warmstart_refine(dg: DeviceGeometry, wall_bd, f: torch.Tensor, x0: torch.Ten
     check(load().warmstart_refine(ctypes.byref(dg.c), wall_bd.h, _ptr(f), _ptr(x0),
                                   ctypes.byref(alpha), _stream(stream)))
     return alpha.value
+
+
+def _geom_array(dgs):
+    arr = (SbieGeom * len(dgs))()
+    for i, dg in enumerate(dgs):
+        arr[i] = dg.c
+    return arr
+
+
+def matvec_batched(dgs, xs, mode: int = 0, stream=None):
+    """y_b = A_b x_b for every member, one launch per stage for the batch."""
+    ys = [torch.empty_like(x) for x in xs]
+    xp = (ctypes.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+    yp = (ctypes.c_void_p * len(ys))(*[_ptr(y) for y in ys])
+    check(load().stokes_dlp_matvec_batched(_geom_array(dgs), len(dgs), xp, yp, mode,
+                                           _stream(stream)))
+    return ys
+
+
+def ifmm_factor_batched(dgs, eps=1e-6, cheb_n=10, leaf_target=64, max_depth=0, precision=0,
+                        workers=4):
+    """IFMM factorisations of every member, several in flight at once."""
+    p = IfmmParams(eps=eps, cheb_n=cheb_n, leaf_target=leaf_target, max_depth=max_depth,
+                   precision=precision)
+    hs = (ctypes.c_void_p * len(dgs))()
+    torch.cuda.synchronize()
+    check(load().ifmm_factor_batched(_geom_array(dgs), len(dgs), ctypes.byref(p), hs, workers))
+    return [IFMM(dg, handle=ctypes.c_void_p(h)) for dg, h in zip(dgs, hs)]
+
+
+def gmres_batched(dgs, fs, pcs=None, tol=1e-10, max_iter=2000, restart=0, x0s=None,
+                  stream=None):
+    """Lockstep FGMRES over the batch; pcs[b] is None, a BlockDiagonal or an IFMM."""
+    nb = len(dgs)
+    pcs = pcs if pcs is not None else [None] * nb
+    sig = [torch.zeros_like(f) if (x0s is None or x0s[b] is None) else x0s[b].clone()
+           for b, f in enumerate(fs)]
+    mem = (GmresMember * nb)()
+    for b, pc in enumerate(pcs):
+        kind = 0 if pc is None else (1 if isinstance(pc, BlockDiagonal) else 2)
+        mem[b] = GmresMember(pc=kind, use_x0=int(x0s is not None and x0s[b] is not None),
+                             bd=pc.h.value if kind == 1 else None,
+                             ifmm=pc.h.value if kind == 2 else None)
+    res = (GmresResult * nb)()
+    fp = (ctypes.c_void_p * nb)(*[_ptr(f) for f in fs])
+    sp = (ctypes.c_void_p * nb)(*[_ptr(x) for x in sig])
+    check(load().gmres_solve_batched(_geom_array(dgs), nb, fp, sp, mem, tol, max_iter, restart,
+                                     res, _stream(stream)))
+    return [SolveResult(sig[b], r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
+                        r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, np.zeros(0))
+            for b, r in enumerate(res)]

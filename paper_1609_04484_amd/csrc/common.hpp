@@ -160,4 +160,28 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
 // Wall length |Gamma_0| into *out (device scalar).
 void wall_length(const sbie_geom *g, double *out, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batched matvec over several geometries (matvec.hip): every stage of y = A x
+// is one launch for all members, each workgroup finding its member from a
+// table of per-member starts.  The per-call member table (pointers, shapes)
+// is staged through pinned memory.
+// ---------------------------------------------------------------------------
+struct BatchMatvec {
+  std::vector<const sbie_geom *> geoms;
+  std::vector<MatvecWork> work;
+  DevBuf<double> scratch;
+  DevBuf<char> desc;
+  char *hdesc = nullptr;
+  hipEvent_t staged = nullptr;   // the last table upload has been consumed
+  size_t desc_cap = 0;
+  int tpt = 4;
+  BatchMatvec(const sbie_geom *const *g, int count);
+  ~BatchMatvec();
+  BatchMatvec(const BatchMatvec &) = delete;
+  BatchMatvec &operator=(const BatchMatvec &) = delete;
+  // y[a] = A_b u[a] for b = members[a]; all members when `members` is empty
+  void run(const std::vector<int> &members, const std::vector<const double *> &u,
+           const std::vector<double *> &y, int mode, hipStream_t s);
+};
+
 }  // namespace sbie

@@ -30,18 +30,12 @@ int g_chunks = 0;     // source chunks (0 = automatic)
 bool g_timing = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 
-__global__ void pack_sources(int64_t nn, int m, const double *__restrict__ x,
-                             const double *__restrict__ y,
-                             const double *__restrict__ nx,
-                             const double *__restrict__ ny,
-                             const double *__restrict__ w,
-                             const double *__restrict__ rad,
-                             const double *__restrict__ cx,
-                             const double *__restrict__ cy,
-                             const double *__restrict__ u,
-                             double *__restrict__ src,
-                             double *__restrict__ psrc) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack_body(int64_t j, int64_t nn, int m, const double *__restrict__ x,
+                                          const double *__restrict__ y, const double *__restrict__ nx,
+                                          const double *__restrict__ ny, const double *__restrict__ w,
+                                          const double *__restrict__ rad, const double *__restrict__ cx,
+                                          const double *__restrict__ cy, const double *__restrict__ u,
+                                          double *__restrict__ src, double *__restrict__ psrc) {
   if (j < nn) {
     const double s = w[j] * (1.0 / kPi);
     double2 *d = reinterpret_cast<double2 *>(src + 8 * j);
@@ -60,13 +54,26 @@ __global__ void pack_sources(int64_t nn, int m, const double *__restrict__ x,
   }
 }
 
+__global__ void pack_sources(int64_t nn, int m, const double *__restrict__ x,
+                             const double *__restrict__ y,
+                             const double *__restrict__ nx,
+                             const double *__restrict__ ny,
+                             const double *__restrict__ w,
+                             const double *__restrict__ rad,
+                             const double *__restrict__ cx,
+                             const double *__restrict__ cy,
+                             const double *__restrict__ u,
+                             double *__restrict__ src,
+                             double *__restrict__ psrc) {
+  pack_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, nn, m, x, y, nx, ny, w, rad, cx, cy, u, src,
+            psrc);
+}
+
 // scal[0] = sum over wall nodes of w (n . sigma); scal[1] = sum of w.
-__global__ void wall_flux(int64_t wall_start, int64_t nn,
-                          const double *__restrict__ nx,
-                          const double *__restrict__ ny,
-                          const double *__restrict__ w,
-                          const double *__restrict__ u, double *scal,
-                          int with_flux) {
+// 1024 threads.
+__device__ __forceinline__ void wall_flux_body(int64_t wall_start, int64_t nn, const double *__restrict__ nx,
+                                               const double *__restrict__ ny, const double *__restrict__ w,
+                                               const double *__restrict__ u, double *scal, int with_flux) {
   __shared__ double sb[1024], sl[1024];
   double b = 0.0, l = 0.0;
   for (int64_t i = wall_start + threadIdx.x; i < nn; i += blockDim.x) {
@@ -87,6 +94,15 @@ __global__ void wall_flux(int64_t wall_start, int64_t nn,
     scal[0] = sb[0];
     scal[1] = sl[0];
   }
+}
+
+__global__ void wall_flux(int64_t wall_start, int64_t nn,
+                          const double *__restrict__ nx,
+                          const double *__restrict__ ny,
+                          const double *__restrict__ w,
+                          const double *__restrict__ u, double *scal,
+                          int with_flux) {
+  wall_flux_body(wall_start, nn, nx, ny, w, u, scal, with_flux);
 }
 
 // s + c += x with the rounding error of the addition carried in c (Knuth's
@@ -135,12 +151,13 @@ __device__ __forceinline__ void batch_recip(const double *d, double *out) {
   }
 }
 
+// One workgroup of the pair sum: target tile `tile` (kBlock * T targets)
+// against source chunk `ch` (sources [ch * chunk, (ch + 1) * chunk)).
 template <int T, bool ACC>
-__global__ __launch_bounds__(kBlock) void dlp_pairs(
-    const double *__restrict__ src, const double *__restrict__ xs,
-    const double *__restrict__ ys, int64_t nn, int64_t chunk,
-    double *__restrict__ part) {
-  const int64_t tile0 = (int64_t)blockIdx.x * (kBlock * T) + threadIdx.x;
+__device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, const double *__restrict__ xs,
+                                               const double *__restrict__ ys, int64_t nn, int64_t chunk,
+                                               double *__restrict__ part, int64_t tile, int64_t ch) {
+  const int64_t tile0 = tile * (kBlock * T) + threadIdx.x;
   double xi[T], yi[T], ax[T], ay[T], cxa[T], cya[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -156,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
     cya[t] = 0.0;
   }
   // uniform loop bounds kept in scalar registers
-  const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * chunk));
+  const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(ch * chunk));
   int64_t j1 = j0 + chunk < nn ? j0 + chunk : nn;
   j1 = __builtin_amdgcn_readfirstlane((int)j1);
   for (int64_t j = j0; j < j1; ++j) {
@@ -187,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
       }
     }
   }
-  double *px = part + (int64_t)blockIdx.y * 4 * nn;
+  double *px = part + ch * 4 * nn;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int64_t i = tile0 + (int64_t)t * kBlock;
@@ -202,18 +219,25 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
   }
 }
 
+template <int T, bool ACC>
+__global__ __launch_bounds__(kBlock) void dlp_pairs(
+    const double *__restrict__ src, const double *__restrict__ xs,
+    const double *__restrict__ ys, int64_t nn, int64_t chunk,
+    double *__restrict__ part) {
+  dlp_pairs_body<T, ACC>(src, xs, ys, nn, chunk, part, blockIdx.x, blockIdx.y);
+}
+
 // Stokeslet + rotlet columns: sum over pores of S(x_i - c_k) lambda_k
 // + r_k R(x_i - c_k) mu_k, without the 1/(4 pi) (applied in the epilogue).
 template <bool ACC>
-__global__ __launch_bounds__(kBlock) void completion_pairs(
-    const double *__restrict__ psrc, const double *__restrict__ xs,
-    const double *__restrict__ ys, int64_t nn, int m,
-    double *__restrict__ part) {
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void completion_body(const double *__restrict__ psrc, const double *__restrict__ xs,
+                                                const double *__restrict__ ys, int64_t nn, int m,
+                                                double *__restrict__ part, int64_t tile, int pc) {
+  const int64_t i0 = tile * kBlock + threadIdx.x;
   const int64_t i = i0 < nn ? i0 : nn - 1;
   const double xi = xs[i], yi = ys[i];
   double ax = 0.0, ay = 0.0, cxa = 0.0, cya = 0.0;
-  const int k0 = blockIdx.y * kPoreChunk;
+  const int k0 = pc * kPoreChunk;
   const int k1 = k0 + kPoreChunk < m ? k0 + kPoreChunk : m;
   for (int k = k0; k < k1; ++k) {
     const double *p = psrc + 8 * k;
@@ -234,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void completion_pairs(
     }
   }
   if (i0 < nn) {
-    double *px = part + (int64_t)blockIdx.y * 4 * nn;
+    double *px = part + (int64_t)pc * 4 * nn;
     px[i0] = ax;
     px[nn + i0] = ay;
     if (ACC) {
@@ -244,17 +268,24 @@ __global__ __launch_bounds__(kBlock) void completion_pairs(
   }
 }
 
-__global__ void epilogue(int64_t nn, int64_t wall_start, int nchunks,
-                         int npchunks, int full, int acc,
-                         const double *__restrict__ part,
-                         const double *__restrict__ nx,
-                         const double *__restrict__ ny,
-                         const double *__restrict__ w,
-                         const double *__restrict__ kappa,
-                         const double *__restrict__ u,
-                         const double *__restrict__ scal,
-                         double *__restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <bool ACC>
+__global__ __launch_bounds__(kBlock) void completion_pairs(
+    const double *__restrict__ psrc, const double *__restrict__ xs,
+    const double *__restrict__ ys, int64_t nn, int m,
+    double *__restrict__ part) {
+  completion_body<ACC>(psrc, xs, ys, nn, m, part, blockIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ void epilogue_body(int64_t i, int64_t nn, int64_t wall_start, int nchunks,
+                                              int npchunks, int full, int acc,
+                                              const double *__restrict__ part,
+                                              const double *__restrict__ nx,
+                                              const double *__restrict__ ny,
+                                              const double *__restrict__ w,
+                                              const double *__restrict__ kappa,
+                                              const double *__restrict__ u,
+                                              const double *__restrict__ scal,
+                                              double *__restrict__ out) {
   if (i >= nn) return;
   // (value, error) pairs; the error parts are only used in the compensated
   // mode, where every addition below is a two-sum
@@ -303,17 +334,30 @@ __global__ void epilogue(int64_t nn, int64_t wall_start, int nchunks,
   out[nn + i] = vy + ey;
 }
 
+__global__ void epilogue(int64_t nn, int64_t wall_start, int nchunks,
+                         int npchunks, int full, int acc,
+                         const double *__restrict__ part,
+                         const double *__restrict__ nx,
+                         const double *__restrict__ ny,
+                         const double *__restrict__ w,
+                         const double *__restrict__ kappa,
+                         const double *__restrict__ u,
+                         const double *__restrict__ scal,
+                         double *__restrict__ out) {
+  epilogue_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, nn, wall_start, nchunks, npchunks, full, acc,
+                part, nx, ny, w, kappa, u, scal, out);
+}
+
 // One wave per pore: the constraint rows lambda_k and mu_k.
-__global__ void pore_rows(int64_t nn, int m, const int64_t *__restrict__ off,
-                          const double *__restrict__ x,
-                          const double *__restrict__ y,
-                          const double *__restrict__ w,
-                          const double *__restrict__ cx,
-                          const double *__restrict__ cy,
-                          const double *__restrict__ rad,
-                          const double *__restrict__ u, int full,
-                          double *__restrict__ out) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void pore_rows_body(int k, int64_t nn, int m, const int64_t *__restrict__ off,
+                                               const double *__restrict__ x,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ w,
+                                               const double *__restrict__ cx,
+                                               const double *__restrict__ cy,
+                                               const double *__restrict__ rad,
+                                               const double *__restrict__ u, int full,
+                                               double *__restrict__ out) {
   if (k >= m) return;
   double sx = 0.0, sy = 0.0, sm = 0.0;
   if (full) {
@@ -343,6 +387,18 @@ __global__ void pore_rows(int64_t nn, int m, const int64_t *__restrict__ off,
       o[0] = o[1] = o[2] = 0.0;
     }
   }
+}
+
+__global__ void pore_rows(int64_t nn, int m, const int64_t *__restrict__ off,
+                          const double *__restrict__ x,
+                          const double *__restrict__ y,
+                          const double *__restrict__ w,
+                          const double *__restrict__ cx,
+                          const double *__restrict__ cy,
+                          const double *__restrict__ rad,
+                          const double *__restrict__ u, int full,
+                          double *__restrict__ out) {
+  pore_rows_body(blockIdx.x, nn, m, off, x, y, w, cx, cy, rad, u, full, out);
 }
 
 __global__ void wall_length_kernel(int64_t wall_start, int64_t nn,
@@ -461,6 +517,196 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched matvec
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BMember {
+  const double *x, *y, *nx, *ny, *w, *kappa, *cx, *cy, *rad;
+  const int64_t *off;
+  int64_t nn, wall_start, chunk, tiles, ctiles;
+  int m, chunks, pchunks, pad;
+  double *src, *psrc, *part, *scal;
+  const double *u;
+  double *out;
+};
+
+enum { kStPack = 0, kStPair, kStComp, kStNode, kStPore, kStages };
+
+// Largest b with st[b] <= unit (members with no units in a stage share the
+// start of the next one and are skipped).
+__device__ __forceinline__ int find_member(const int64_t *__restrict__ st, int nb, int64_t unit) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid] <= unit) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void pack_b(const BMember *__restrict__ d, const int64_t *__restrict__ st, int nb) {
+  const int b = find_member(st, nb, blockIdx.x);
+  const BMember &M = d[b];
+  const int64_t j = ((int64_t)blockIdx.x - st[b]) * blockDim.x + threadIdx.x;
+  pack_body(j, M.nn, M.m, M.x, M.y, M.nx, M.ny, M.w, M.rad, M.cx, M.cy, M.u, M.src, M.psrc);
+}
+
+__global__ void wall_flux_b(const BMember *__restrict__ d) {
+  const BMember &M = d[blockIdx.x];
+  wall_flux_body(M.wall_start, M.nn, M.nx, M.ny, M.w, M.u, M.scal, 1);
+}
+
+template <int T, bool ACC>
+__global__ __launch_bounds__(kBlock) void dlp_pairs_b(const BMember *__restrict__ d,
+                                                      const int64_t *__restrict__ st, int nb) {
+  const int b = find_member(st, nb, blockIdx.x);
+  const BMember &M = d[b];
+  const int64_t u = (int64_t)blockIdx.x - st[b];
+  dlp_pairs_body<T, ACC>(M.src, M.x, M.y, M.nn, M.chunk, M.part, u % M.tiles, u / M.tiles);
+}
+
+template <bool ACC>
+__global__ __launch_bounds__(kBlock) void completion_b(const BMember *__restrict__ d,
+                                                       const int64_t *__restrict__ st, int nb) {
+  const int b = find_member(st, nb, blockIdx.x);
+  const BMember &M = d[b];
+  const int64_t u = (int64_t)blockIdx.x - st[b];
+  completion_body<ACC>(M.psrc, M.x, M.y, M.nn, M.m, M.part + (int64_t)M.chunks * 4 * M.nn,
+                       u % M.ctiles, (int)(u / M.ctiles));
+}
+
+__global__ void epilogue_b(const BMember *__restrict__ d, const int64_t *__restrict__ st, int nb, int full,
+                           int acc) {
+  const int b = find_member(st, nb, blockIdx.x);
+  const BMember &M = d[b];
+  const int64_t i = ((int64_t)blockIdx.x - st[b]) * blockDim.x + threadIdx.x;
+  epilogue_body(i, M.nn, M.wall_start, M.chunks, full ? M.pchunks : 0, full, acc, M.part, M.nx, M.ny, M.w,
+                M.kappa, M.u, M.scal, M.out);
+}
+
+__global__ void pore_rows_b(const BMember *__restrict__ d, const int64_t *__restrict__ st, int nb, int full) {
+  const int b = find_member(st, nb, blockIdx.x);
+  const BMember &M = d[b];
+  pore_rows_body((int)(blockIdx.x - st[b]), M.nn, M.m, M.off, M.x, M.y, M.w, M.cx, M.cy, M.rad, M.u, full,
+                 M.out);
+}
+
+}  // namespace
+
+BatchMatvec::BatchMatvec(const sbie_geom *const *g, int count) {
+  tpt = g_tpt;
+  size_t total = 0;
+  std::vector<size_t> offs;
+  for (int b = 0; b < count; ++b) {
+    geoms.push_back(g[b]);
+    work.push_back(plan_matvec(g[b]));
+    work.back().tpt = tpt;
+    offs.push_back(total);
+    total += (matvec_scratch_doubles(work.back(), g[b]) + 31) & ~size_t(31);
+  }
+  scratch.alloc(total);
+  for (int b = 0; b < count; ++b) bind_matvec_scratch(work[b], g[b], scratch.p + offs[b]);
+  desc_cap = (size_t)count * sizeof(BMember) + (size_t)kStages * (count + 1) * sizeof(int64_t) + 256;
+  desc.alloc(desc_cap);
+  SBIE_HIP(hipHostMalloc((void **)&hdesc, desc_cap, hipHostMallocDefault));
+  SBIE_HIP(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+}
+
+BatchMatvec::~BatchMatvec() {
+  if (staged) {
+    (void)hipEventSynchronize(staged);
+    (void)hipEventDestroy(staged);
+  }
+  if (hdesc) (void)hipHostFree(hdesc);
+}
+
+void BatchMatvec::run(const std::vector<int> &members, const std::vector<const double *> &u,
+                      const std::vector<double *> &y, int mode, hipStream_t s) {
+  std::vector<int> mem = members;
+  if (mem.empty())
+    for (int b = 0; b < (int)geoms.size(); ++b) mem.push_back(b);
+  const int nb = (int)mem.size();
+  if (nb == 0) return;
+  if ((int)u.size() != nb || (int)y.size() != nb) fail(SBIE_INVALID_ARGUMENT, "batched matvec: vector count");
+  const int full = mode == SBIE_MV_FULL || mode == SBIE_MV_FULL_ACCURATE;
+  const bool acc = mode == SBIE_MV_FULL_ACCURATE;
+  const int T = acc ? 1 : tpt;
+  // the previous table must have reached the device before it is rewritten
+  SBIE_HIP(hipEventSynchronize(staged));
+  BMember *hd = reinterpret_cast<BMember *>(hdesc);
+  int64_t *hst = reinterpret_cast<int64_t *>(hdesc + (size_t)nb * sizeof(BMember));
+  int64_t acc_st[kStages] = {0, 0, 0, 0, 0};
+  for (int a = 0; a < nb; ++a) {
+    const sbie_geom *g = geoms[mem[a]];
+    const MatvecWork &w = work[mem[a]];
+    BMember &M = hd[a];
+    M.x = g->x; M.y = g->y; M.nx = g->nx; M.ny = g->ny; M.w = g->w; M.kappa = g->kappa;
+    M.cx = g->cx; M.cy = g->cy; M.rad = g->radius; M.off = g->curve_off_dev;
+    M.nn = g->n_nodes;
+    M.m = g->n_pores;
+    M.wall_start = g->curve_off[g->n_pores];
+    M.chunks = w.chunks;
+    M.pchunks = w.pchunks;
+    M.pad = 0;
+    M.chunk = (M.nn + w.chunks - 1) / w.chunks;
+    M.tiles = ceil_div(M.nn, (int64_t)kBlock * T);
+    M.ctiles = ceil_div(M.nn, kBlock);
+    M.src = w.src; M.psrc = w.psrc; M.part = w.part; M.scal = w.scal;
+    M.u = u[a];
+    M.out = y[a];
+    const int64_t units[kStages] = {
+        (int64_t)ceil_div(M.nn > M.m ? M.nn : M.m, 256), M.tiles * M.chunks,
+        (full && M.m > 0) ? M.ctiles * M.pchunks : 0, (int64_t)ceil_div(M.nn, 256), (int64_t)M.m};
+    for (int q = 0; q < kStages; ++q) {
+      hst[(size_t)q * (nb + 1) + a] = acc_st[q];
+      acc_st[q] += units[q];
+    }
+  }
+  for (int q = 0; q < kStages; ++q) hst[(size_t)q * (nb + 1) + nb] = acc_st[q];
+  const size_t bytes = (size_t)nb * sizeof(BMember) + (size_t)kStages * (nb + 1) * sizeof(int64_t);
+  SBIE_HIP(hipMemcpyAsync(desc.p, hdesc, bytes, hipMemcpyHostToDevice, s));
+  SBIE_HIP(hipEventRecord(staged, s));
+  const BMember *dd = reinterpret_cast<const BMember *>(desc.p);
+  const int64_t *dst = reinterpret_cast<const int64_t *>(desc.p + (size_t)nb * sizeof(BMember));
+  auto stt = [&](int q) { return dst + (size_t)q * (nb + 1); };
+  auto grid = [&](int q) -> unsigned {
+    if (acc_st[q] > (int64_t)0x7fffffff) fail(SBIE_INVALID_ARGUMENT, "batch too large for one launch");
+    return (unsigned)acc_st[q];
+  };
+  pack_b<<<grid(kStPack), 256, 0, s>>>(dd, stt(kStPack), nb);
+  SBIE_LAUNCH_CHECK();
+  if (full) {
+    wall_flux_b<<<nb, 1024, 0, s>>>(dd);
+    SBIE_LAUNCH_CHECK();
+  }
+  if (acc) {
+    dlp_pairs_b<1, true><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb);
+  } else {
+    switch (T) {
+      case 1: dlp_pairs_b<1, false><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb); break;
+      case 2: dlp_pairs_b<2, false><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb); break;
+      case 4: dlp_pairs_b<4, false><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb); break;
+      case 8: dlp_pairs_b<8, false><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb); break;
+      default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
+    }
+  }
+  SBIE_LAUNCH_CHECK();
+  if (acc_st[kStComp] > 0) {
+    if (acc)
+      completion_b<true><<<grid(kStComp), kBlock, 0, s>>>(dd, stt(kStComp), nb);
+    else
+      completion_b<false><<<grid(kStComp), kBlock, 0, s>>>(dd, stt(kStComp), nb);
+    SBIE_LAUNCH_CHECK();
+  }
+  epilogue_b<<<grid(kStNode), 256, 0, s>>>(dd, stt(kStNode), nb, full, acc ? 1 : 0);
+  SBIE_LAUNCH_CHECK();
+  if (acc_st[kStPore] > 0) {
+    pore_rows_b<<<grid(kStPore), 64, 0, s>>>(dd, stt(kStPore), nb, full);
+    SBIE_LAUNCH_CHECK();
+  }
+}
+
 void wall_length(const sbie_geom *g, double *out, hipStream_t s) {
   wall_length_kernel<<<1, 256, 0, s>>>(g->curve_off[g->n_pores], g->n_nodes,
                                        g->w, out);
@@ -484,6 +730,33 @@ extern "C" int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y,
     sbie::StreamBuf<double> scratch(sbie::matvec_scratch_doubles(w, g), s);
     sbie::bind_matvec_scratch(w, g, scratch.p);
     sbie::matvec_run(g, x, y, mode, w, s);
+    return SBIE_OK;
+  });
+}
+
+extern "C" int stokes_dlp_matvec_batched(const sbie_geom *geoms, int32_t count, const double *const *x,
+                                         double *const *y, int mode, void *stream) {
+  return sbie::guarded([&]() {
+    if (count < 0 || (count > 0 && (!geoms || !x || !y))) sbie::fail(SBIE_INVALID_ARGUMENT, "bad batch");
+    if (mode != SBIE_MV_FULL && mode != SBIE_MV_DLP_ONLY && mode != SBIE_MV_FULL_ACCURATE)
+      sbie::fail(SBIE_INVALID_ARGUMENT, "unknown matvec mode %d", mode);
+    if (count == 0) return SBIE_OK;
+    std::vector<const sbie_geom *> gp;
+    std::vector<const double *> u;
+    std::vector<double *> out;
+    for (int b = 0; b < count; ++b) {
+      sbie::validate_geom(&geoms[b]);
+      if (!x[b] || !y[b]) sbie::fail(SBIE_INVALID_ARGUMENT, "null vector for member %d", b);
+      const int64_t n = sbie::n_unknowns(&geoms[b]);
+      if (x[b] < y[b] + n && y[b] < x[b] + n) sbie::fail(SBIE_INVALID_ARGUMENT, "x and y overlap (member %d)", b);
+      gp.push_back(&geoms[b]);
+      u.push_back(x[b]);
+      out.push_back(y[b]);
+    }
+    sbie::BatchMatvec bm(gp.data(), count);
+    bm.run({}, u, out, mode, (hipStream_t)stream);
+    // the batch's scratch is freed on return: wait for its kernels
+    SBIE_HIP(hipStreamSynchronize((hipStream_t)stream));
     return SBIE_OK;
   });
 }

@@ -1,0 +1,170 @@
+"""Batched entry points: the batched matvec equals the single-geometry one
+(same arithmetic and order, so bit for bit) and the dense oracle; the
+lockstep FGMRES reaches each member's solution with the iteration count of
+the single solve; concurrent IFMM factorisations equal sequential ones; the
+autotuner's choices keep results within rounding."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dlp, solve
+from stokes_inputs import (Geometry, batch_member, build_geometry, make_geometry,
+                           poiseuille_rhs, random_vector, stokeslet_rotlet_rhs)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(length=4.0, n_ext=512, n_pores=30, r_lo=0.03, r_hi=0.06, n_int=64,
+             gap_pore=0.02, gap_wall=0.08)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1609_04484_amd as p
+    p.load()
+    return p
+
+
+def single_circle(n, r=0.3):
+    th = 2 * math.pi * np.arange(n) / n
+    c, s = np.cos(th), np.sin(th)
+    return Geometry(x=r * c, y=r * s, nx=-c, ny=-s, tx=-s, ty=c,
+                    w=np.full(n, 2 * math.pi * r / n), kappa=np.full(n, 1 / r),
+                    cx=np.array([0.0]), cy=np.array([0.0]), radius=np.array([r]),
+                    curve_off=np.array([0, n, n]), length=1.0, n_int=n, n_ext=0)
+
+
+def members():
+    """Ragged sizes and the degenerate cases: no wall, no pores, one pore."""
+    return [make_geometry("tiny", 1), single_circle(37),
+            build_geometry(3.0, 130, [], [], [], 0), make_geometry(SMALL, 5),
+            make_geometry(dict(SMALL, n_pores=7, n_int=40), 8)]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_matvec_batched_equals_single(lib, mode):
+    gs = members()
+    dgs = [lib.DeviceGeometry(g) for g in gs]
+    xs = [dg.vector(random_vector(g.n_unknowns, 10 + b)) for b, (g, dg) in enumerate(zip(gs, dgs))]
+    ys = lib.matvec_batched(dgs, xs, mode)
+    for g, dg, x, y in zip(gs, dgs, xs, ys):
+        ref = lib.matvec(dg, x, mode)
+        assert torch.equal(y, ref), g.n_unknowns
+
+
+def test_matvec_batched_matches_oracle(lib):
+    gs = members()[:3]
+    dgs = [lib.DeviceGeometry(g) for g in gs]
+    xs_h = [random_vector(g.n_unknowns, 20 + b) for b, g in enumerate(gs)]
+    ys = lib.matvec_batched(dgs, [dg.vector(x) for dg, x in zip(dgs, xs_h)])
+    for g, x, y in zip(gs, xs_h, ys):
+        ref = dlp.assemble(g) @ x
+        assert np.abs(y.cpu().numpy() - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_matvec_batched_many_members(lib):
+    """More members than one wave of the member search, uneven sizes."""
+    gs = [make_geometry(dict(SMALL, n_pores=3 + (b % 5), length=2.0 + 0.1 * b), 30 + b)
+          for b in range(70)]
+    dgs = [lib.DeviceGeometry(g) for g in gs]
+    xs = [dg.vector(random_vector(g.n_unknowns, b)) for b, (g, dg) in enumerate(zip(gs, dgs))]
+    ys = lib.matvec_batched(dgs, xs)
+    for dg, x, y in zip(dgs, xs, ys):
+        assert torch.equal(y, lib.matvec(dg, x))
+
+
+def test_gmres_batched_matches_single(lib):
+    gs = [make_geometry("tiny", 1), make_geometry(SMALL, 5), make_geometry(SMALL, 6),
+          make_geometry(dict(SMALL, n_pores=12), 7)]
+    dgs = [lib.DeviceGeometry(g) for g in gs]
+    fs = [dg.vector(poiseuille_rhs(g)) for g, dg in zip(gs, dgs)]
+    pcs = [None, lib.BlockDiagonal(dgs[1]), lib.IFMM(dgs[2], eps=1e-4, cheb_n=8),
+           lib.IFMM(dgs[3], eps=1e-3, cheb_n=6, precision=1)]
+    rb = lib.gmres_batched(dgs, fs, pcs, tol=1e-10)
+    for g, dg, f, pc, r in zip(gs, dgs, fs, pcs, rb):
+        ref = lib.gmres(dg, f, pc=pc, tol=1e-10)
+        assert r.status == 0 and r.rel_res_true <= 1e-10
+        assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+        d = torch.linalg.vector_norm(r.sigma - ref.sigma) / torch.linalg.vector_norm(ref.sigma)
+        assert float(d) < 1e-8
+    # and the first member against the dense LU solution
+    sig = solve.lu_solve(dlp.assemble(gs[0]), poiseuille_rhs(gs[0]))
+    assert np.linalg.norm(rb[0].sigma.cpu().numpy() - sig) / np.linalg.norm(sig) < 1e-8
+
+
+def test_gmres_batched_restart_and_degenerate_members(lib):
+    """Restarted cycles of different lengths, a zero right-hand side, an
+    exact initial guess and an iteration cap, in one batch."""
+    g = make_geometry("tiny", 1)
+    a = dlp.assemble(g)
+    f, _ = stokeslet_rotlet_rhs(g, 1)
+    sig = solve.lu_solve(a, f)
+    dgs = [lib.DeviceGeometry(g) for _ in range(4)]
+    fs = [dgs[0].vector(f), dgs[1].vector(np.zeros_like(f)), dgs[2].vector(f), dgs[3].vector(f)]
+    x0s = [None, None, dgs[2].vector(sig), None]
+    pcs = [lib.BlockDiagonal(dgs[0]), None, None, lib.BlockDiagonal(dgs[3])]
+    rb = lib.gmres_batched(dgs, fs, pcs, tol=1e-11, restart=7, x0s=x0s, max_iter=400)
+    ref = lib.gmres(dgs[0], fs[0], pc=pcs[0], tol=1e-11, restart=7, max_iter=400)
+    assert rb[0].status == 0 and abs(rb[0].iters - ref.iters) <= max(2, ref.iters // 10)
+    assert rb[1].status == 0 and rb[1].iters == 0 and float(rb[1].sigma.abs().max()) == 0.0
+    assert rb[2].iters == 0 and rb[2].status == 0
+    assert rb[3].status == 0 and rb[3].iters == rb[0].iters
+    capped = lib.gmres_batched(dgs[:1], fs[:1], [None], tol=1e-14, max_iter=3)
+    assert capped[0].status == 1 and capped[0].iters == 3
+
+
+def test_gmres_batched_rejects_bad_members(lib):
+    g = make_geometry("tiny", 1)
+    dg = lib.DeviceGeometry(g)
+    f = dg.vector(poiseuille_rhs(g))
+    with pytest.raises(lib.SbieError):
+        lib.gmres_batched([dg], [f], [None], tol=-1.0)
+    nonfinite = f.clone()
+    nonfinite[3] = float("nan")
+    with pytest.raises(lib.SbieError):
+        lib.gmres_batched([dg, dg], [f, nonfinite], [None, None])
+
+
+def test_ifmm_factor_batched_equals_sequential(lib):
+    gs = [make_geometry(SMALL, 5), make_geometry("tiny", 1), make_geometry(SMALL, 9),
+          make_geometry(dict(SMALL, n_pores=12), 7), make_geometry(SMALL, 11)]
+    dgs = [lib.DeviceGeometry(g) for g in gs]
+    pcs = lib.ifmm_factor_batched(dgs, eps=1e-4, cheb_n=8, workers=3)
+    for g, dg, pc in zip(gs, dgs, pcs):
+        ref = lib.IFMM(dg, eps=1e-4, cheb_n=8)
+        v = dg.vector(random_vector(g.n_unknowns, 3))
+        a, b = pc.solve(v), ref.solve(v)
+        assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) < 1e-12
+        assert pc.stats()["levels"] == ref.stats()["levels"]
+    with pytest.raises(lib.SbieError):
+        lib.ifmm_factor_batched(dgs, workers=0)
+
+
+def test_autotuner_shape_and_cache(lib, tmp_path):
+    from paper_1609_04484_amd.autotune import Autotuner
+    g = make_geometry(SMALL, 5)
+    dg = lib.DeviceGeometry(g)
+    x = dg.vector(random_vector(g.n_unknowns, 4))
+    ref = lib.matvec(dg, x)
+    path = str(tmp_path / "tune.json")
+    at = Autotuner(path)
+    shape = at.matvec_shape(dg, reps=2, candidates=[(1, 0), (4, 0), (8, 32), (2, 64)])
+    assert shape in [(1, 0), (4, 0), (8, 32), (2, 64)]
+    try:
+        lib.set_matvec_shape(*shape)
+        y = lib.matvec(dg, x)
+    finally:
+        lib.set_matvec_shape(4, 0)
+    assert float((y - ref).abs().max() / ref.abs().max()) < 1e-13
+    assert Autotuner(path).matvec_shape(dg) == shape          # cached, not re-measured
+    f = dg.vector(poiseuille_rhs(g))
+    eps, cn = at.ifmm_params(dg, f, candidates=[(1e-3, 6), (1e-4, 8)])
+    assert (eps, cn) in [(1e-3, 6), (1e-4, 8)]
+
+
+def test_batch_member_recipe_sizes():
+    sizes = [batch_member(s).n_unknowns for s in range(5000, 5008)]
+    assert min(sizes) >= 1000 and max(sizes) <= 61000
