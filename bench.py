@@ -25,6 +25,24 @@ METRIC = ("GMRES solves/s to rel. residual 1e-10 at N≈128k: IFMM vs block-diag
 FP64_VECTOR_PEAK = 78.6e12     # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 PAIR_FLOPS = 19                # algorithmic flops per node pair of the matvec
 
+# HBM bytes per launch of the pair kernel at the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors
+# read off a plain 1 GiB device copy; profiles/dlp_pairs_pipe1000_hbm_counters.md).
+# Valid only for the kernel source they were taken with: reported as null
+# once matvec.hip changes.
+PAIR_TRAFFIC = {"matvec_sha256": "03bc71a11aa8fa0cef28c73ed33c4bf20b0d75e6935f66b59f3eb8ce7b699241", "bytes_per_launch": 196028826,
+                "workload": "pipe1000"}
+
+
+def pair_traffic(workload):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1609_04484_amd", "csrc", "matvec.hip")
+    with open(path, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if sha != PAIR_TRAFFIC["matvec_sha256"] or workload != PAIR_TRAFFIC["workload"]:
+        return None
+    return PAIR_TRAFFIC["bytes_per_launch"]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -37,17 +55,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pipe1000")
     ap.add_argument("--seed", type=int, default=300)
-    ap.add_argument("--pc", default="both", choices=["ifmm", "bd", "both"])
+    ap.add_argument("--pc", default="all", choices=["ifmm", "bd", "both", "all"],
+                    help="ifmm: IFMM at --ifmm-precision; both: that and block-diagonal; "
+                         "all: IFMM in FP64 and in FP32, and block-diagonal")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--cheb-n", type=int, default=8)
-    ap.add_argument("--ifmm-precision", type=int, default=1,
+    ap.add_argument("--ifmm-precision", type=int, default=0,
                     help="0 = FP64 factor/apply, 1 = FP32 (mixed precision)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--matvec-only", type=int, default=0,
                     help="time this many plain matvecs instead of solves (profiling runs)")
+    ap.add_argument("--tpt", type=int, default=0,
+                    help="pair-kernel targets per thread (0 = library default)")
+    ap.add_argument("--chunks", type=int, default=0,
+                    help="pair-kernel source chunks (0 = the library's occupancy-based choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=512)
     args = ap.parse_args()
@@ -64,6 +88,8 @@ def main():
     from stokes_inputs import make_geometry, poiseuille_rhs
 
     torch.cuda.set_device(0)
+    if args.tpt or args.chunks:
+        lib.set_matvec_shape(args.tpt or 4, args.chunks)
     g = make_geometry(args.workload, args.seed)
     f = poiseuille_rhs(g)
     dg = lib.DeviceGeometry(g)
@@ -102,9 +128,10 @@ def main():
     def make_pc(kind):
         if kind == "bd":
             return lib.BlockDiagonal(dg)
-        return lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=args.ifmm_precision)
+        prec = {"ifmm": args.ifmm_precision, "ifmm_fp64": 0, "ifmm_fp32": 1}[kind]
+        return lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=prec)
 
-    kinds = ["ifmm", "bd"] if args.pc == "both" else [args.pc]
+    kinds = {"both": ["ifmm", "bd"], "all": ["ifmm_fp64", "ifmm_fp32", "bd"]}.get(args.pc, [args.pc])
     results = {}
     for kind in kinds:
         try:
@@ -131,7 +158,7 @@ def main():
             torch.cuda.synchronize()
             tfac.append(time.perf_counter() - tf0)
             r = lib.gmres(dg, fd, pc=pc, tol=args.tol, max_iter=args.max_iter)
-            stats = pc.stats() if kind == "ifmm" else None
+            stats = pc.stats() if kind != "bd" else None
             pc.close()
             iters.append(r.iters)
             relres.append(r.rel_res_true)
@@ -168,7 +195,8 @@ def main():
     if not results:
         print("no preconditioner could be built", file=sys.stderr)
         sys.exit(1)
-    head = "ifmm" if "ifmm" in results else "bd"
+    ifmm_kinds = [k for k in results if k != "bd"]
+    head = max(ifmm_kinds, key=lambda k: results[k]["solves_per_s"]) if ifmm_kinds else "bd"
     hr = results[head]
 
     # sampled-row check of the last solution against the oracle's rows
@@ -183,8 +211,8 @@ def main():
     achieved = PAIR_FLOPS * float(nn) ** 2 / (kernel_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": "dlp_pairs", "achieved": achieved / 1e12,
                 "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
-                "avg_kernel_ms": kernel_ms}
+                "frac": achieved / FP64_VECTOR_PEAK, "traffic": pair_traffic(args.workload),
+                "traffic_unit": "HBM bytes per launch", "avg_kernel_ms": kernel_ms}
     matvec_gbs = 32.0 * float(nn) ** 2 / (hr["t_matvec_s"] / max(1, np.mean(hr["iters"]))) / 1e9
 
     cpu = None
@@ -226,9 +254,13 @@ def main():
         "config": {"workload": f"{args.workload}: pipe [0,50]x[0,1], 4096 wall nodes, "
                                f"1000 pores x 64 nodes, Poiseuille inflow",
                    "seed": args.seed, "n_unknowns": n, "pc": head, "tol": args.tol,
-                   "ifmm_eps": args.eps if head == "ifmm" else None,
-                   "ifmm_cheb_n": args.cheb_n if head == "ifmm" else None,
-                   "ifmm_precision": ("fp32" if args.ifmm_precision else "fp64") if head == "ifmm" else None},
+                   "ifmm_eps": args.eps if head != "bd" else None,
+                   "ifmm_cheb_n": args.cheb_n if head != "bd" else None,
+                   "ifmm_precision": {"ifmm_fp64": "fp64", "ifmm_fp32": "fp32",
+                                      "ifmm": "fp32" if args.ifmm_precision else "fp64"}.get(head),
+                   "matvec_arnoldi_residual_dtype": "f64"},
+        "speedup_vs_block_diagonal": (hr["solves_per_s"] / results["bd"]["solves_per_s"]
+                                      if "bd" in results and head != "bd" else None),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solves": results,

@@ -2,12 +2,16 @@
 // factorisation is a long sequence of small launches separated by host
 // synchronisation points (elimination phases, rank decisions), so a single
 // one leaves most of the device idle; several host threads, each driving its
-// own stream, keep several members in flight at once.
+// own stream, keep several members in flight at once.  The HIP graphs of
+// the applications are captured afterwards, one after the other, by the
+// calling thread: a capture must not overlap allocations, frees or
+// synchronisations issued by other threads.
 #include <atomic>
 #include <mutex>
 #include <thread>
 
 #include "common.hpp"
+#include "precond.hpp"
 
 extern "C" int ifmm_factor_batched(const sbie_geom *geoms, int32_t count, const ifmm_params *params,
                                    ifmm_handle **out, int32_t workers) {
@@ -41,8 +45,15 @@ extern "C" int ifmm_factor_batched(const sbie_geom *geoms, int32_t count, const 
           std::lock_guard<std::mutex> lk(mu);
           if (first_code != SBIE_OK) break;
         }
-        code = ifmm_factor(&geoms[b], params, &out[b], s);
-        if (code != SBIE_OK) msg = std::string("member ") + std::to_string(b) + ": " + sbie_last_error();
+        try {
+          out[b] = sbie::ifmm_factor_internal(&geoms[b], params, s, true);
+        } catch (const sbie::Error &e) {
+          code = e.code;
+          msg = std::string("member ") + std::to_string(b) + ": " + e.what();
+        } catch (const std::exception &e) {
+          code = SBIE_HIP_ERROR;
+          msg = std::string("member ") + std::to_string(b) + ": " + e.what();
+        }
       }
       if (s) {
         (void)hipStreamSynchronize(s);
@@ -60,12 +71,21 @@ extern "C" int ifmm_factor_batched(const sbie_geom *geoms, int32_t count, const 
     std::vector<std::thread> pool;
     for (int t = 0; t < nw; ++t) pool.emplace_back(work);
     for (auto &t : pool) t.join();
-    if (first_code != SBIE_OK) {
+    auto destroy_all = [&]() {
       for (int b = 0; b < count; ++b) {
         if (out[b]) ifmm_destroy(out[b]);
         out[b] = nullptr;
       }
+    };
+    if (first_code != SBIE_OK) {
+      destroy_all();
       sbie::fail(first_code, "%s", first_msg.c_str());
+    }
+    try {
+      for (int b = 0; b < count; ++b) sbie::ifmm_capture(out[b]);
+    } catch (...) {
+      destroy_all();
+      throw;
     }
     return (int)SBIE_OK;
   });

@@ -477,6 +477,11 @@ struct StageClock {
 struct IfmmImplBase {
   virtual ~IfmmImplBase() = default;
   virtual void apply(const double *b, double *x, hipStream_t s) const = 0;
+  // capture the application into a HIP graph (done by factor unless
+  // defer_graph is set, in which case the caller captures later, from a
+  // thread while no other thread works on the device)
+  virtual void capture_graph() = 0;
+  bool defer_graph = false;
   ifmm_stats stats{};
   int64_t n = 0;
 };
@@ -516,6 +521,8 @@ struct IfmmImpl : IfmmImplBase {
     SBIE_HIP(hipStreamEndCapture(cap_stream, &graph));
     SBIE_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
   }
+
+  void capture_graph() override { build_graph(); }
 
   void apply(const double *b, double *x, hipStream_t s) const override {
     const int64_t nd = n_leaf_dofs;
@@ -1335,7 +1342,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   SBIE_HIP(hipStreamSynchronize(s));
   clk.tick("root");
   level_arena.reset();
-  build_graph();
+  if (!defer_graph) build_graph();
   clk.tick("graph");
   stats.levels = tr.depth + 1;
   stats.leaves = nleaf;
@@ -1358,26 +1365,42 @@ void ifmm_apply(const ifmm_handle *h, const double *b, double *x, hipStream_t s)
 }
 }  // namespace sbie
 
+namespace sbie {
+ifmm_handle *ifmm_factor_internal(const sbie_geom *g, const ifmm_params *p, hipStream_t s,
+                                  bool defer_graph) {
+  validate_geom(g);
+  if (!p) fail(SBIE_INVALID_ARGUMENT, "null pointer");
+  auto h = std::make_unique<ifmm_handle>();
+  if (p->precision == 0) {
+    auto impl = std::make_unique<IfmmImpl<double>>();
+    impl->defer_graph = defer_graph;
+    impl->factor(g, p, s);
+    h->impl = std::move(impl);
+  } else if (p->precision == 1) {
+    auto impl = std::make_unique<IfmmImpl<float>>();
+    impl->defer_graph = defer_graph;
+    impl->factor(g, p, s);
+    h->impl = std::move(impl);
+  } else {
+    fail(SBIE_INVALID_ARGUMENT, "precision must be 0 (FP64) or 1 (FP32)");
+  }
+  return h.release();
+}
+
+void ifmm_capture(ifmm_handle *h) {
+  if (h->impl->defer_graph) {
+    h->impl->capture_graph();
+    h->impl->defer_graph = false;
+  }
+}
+}  // namespace sbie
+
 extern "C" int ifmm_factor(const sbie_geom *g, const ifmm_params *p, ifmm_handle **out,
                            void *stream) {
   return sbie::guarded([&]() {
-    sbie::validate_geom(g);
-    if (!p || !out) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
+    if (!out) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
     *out = nullptr;
-    auto h = std::make_unique<ifmm_handle>();
-    hipStream_t s = (hipStream_t)stream;
-    if (p->precision == 0) {
-      auto impl = std::make_unique<sbie::IfmmImpl<double>>();
-      impl->factor(g, p, s);
-      h->impl = std::move(impl);
-    } else if (p->precision == 1) {
-      auto impl = std::make_unique<sbie::IfmmImpl<float>>();
-      impl->factor(g, p, s);
-      h->impl = std::move(impl);
-    } else {
-      sbie::fail(SBIE_INVALID_ARGUMENT, "precision must be 0 (FP64) or 1 (FP32)");
-    }
-    *out = h.release();
+    *out = sbie::ifmm_factor_internal(g, p, (hipStream_t)stream, false);
     return SBIE_OK;
   });
 }

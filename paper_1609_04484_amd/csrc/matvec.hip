@@ -14,6 +14,10 @@
 //   epilogue          sums the partials, adds the jump, the smooth diagonal
 //                     limit and the wall rank-one term
 //   pore_rows         the three constraint rows per pore (one wave per pore)
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 
 namespace sbie {
@@ -127,17 +131,18 @@ __device__ __forceinline__ double recip(double d) {
 // Reciprocals of T positive numbers with one hardware reciprocal: the
 // product of all of them is inverted (and refined) once, and each 1/d_t is
 // recovered as that inverse times the product of the others (Montgomery's
-// batch-inversion trick).  The d_t are squared distances between nodes, so
-// their product stays far inside the FP64 range.
+// batch-inversion trick).  The d_t are squared distances between nodes (at
+// least 1e-100), so a product of up to eight stays far inside the FP64
+// range for any domain smaller than about 1e18.
 template <int T>
 __device__ __forceinline__ void batch_recip(const double *d, double *out) {
-  if (T == 1) {
+  if constexpr (T == 1) {
     out[0] = recip(d[0]);
-  } else if (T == 2) {
+  } else if constexpr (T == 2) {
     const double r = recip(d[0] * d[1]);
     out[0] = r * d[1];
     out[1] = r * d[0];
-  } else if (T == 4) {
+  } else if constexpr (T == 4) {
     const double p01 = d[0] * d[1], p23 = d[2] * d[3];
     const double r = recip(p01 * p23);
     const double r01 = r * p23, r23 = r * p01;
@@ -145,18 +150,87 @@ __device__ __forceinline__ void batch_recip(const double *d, double *out) {
     out[1] = r01 * d[0];
     out[2] = r23 * d[3];
     out[3] = r23 * d[2];
+  } else if constexpr (T == 8) {
+    // product tree over eight values, one refined reciprocal, then the
+    // partial products recover every 1/d_t
+    const double p01 = d[0] * d[1], p23 = d[2] * d[3], p45 = d[4] * d[5], p67 = d[6] * d[7];
+    const double p03 = p01 * p23, p47 = p45 * p67;
+    const double r = recip(p03 * p47);
+    const double r03 = r * p47, r47 = r * p03;
+    const double r01 = r03 * p23, r23 = r03 * p01, r45 = r47 * p67, r67 = r47 * p45;
+    out[0] = r01 * d[1];
+    out[1] = r01 * d[0];
+    out[2] = r23 * d[3];
+    out[3] = r23 * d[2];
+    out[4] = r45 * d[5];
+    out[5] = r45 * d[4];
+    out[6] = r67 * d[7];
+    out[7] = r67 * d[6];
   } else {
 #pragma unroll
-    for (int h = 0; h < T; h += 4) batch_recip<4>(d + h, out + h);
+    for (int h = 0; h < T; h += 8) batch_recip<8>(d + h, out + h);
   }
 }
 
+// The contribution of one source record to T targets, with the
+// reciprocals of S consecutive sources batched together (S * T values).
+template <int T, int S, bool ACC>
+__device__ __forceinline__ void pair_step(const double *__restrict__ src, int j, const double *xi,
+                                          const double *yi, double *ax, double *ay, double *cxa,
+                                          double *cya) {
+  double sx[S], sy[S], sax[S], say[S], ssx[S], ssy[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const double *s = src + 8 * (int64_t)(j + q);  // wave-uniform: scalar loads
+    sx[q] = s[0];
+    sy[q] = s[1];
+    sax[q] = s[2];
+    say[q] = s[3];
+    ssx[q] = s[4];
+    ssy[q] = s[5];
+  }
+  double rx[S * T], ry[S * T], r2[S * T], inv[S * T];
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int u = q * T + t;
+      rx[u] = xi[t] - sx[q];
+      ry[u] = yi[t] - sy[q];
+      // the self pair has r = 0 exactly: the 1e-100 added inside the fused
+      // multiply-add keeps 1/rho^4 finite there (the pair's factors
+      // (r.a)(r.sigma) are exactly zero) and is below half an ulp of rho^2
+      // for every other pair, so it changes no other result
+      r2[u] = fma(ry[u], ry[u], fma(rx[u], rx[u], 1e-100));
+    }
+  batch_recip<S * T>(r2, inv);
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int u = q * T + t;
+      const double dn = fma(ry[u], say[q], rx[u] * sax[q]);
+      const double ds = fma(ry[u], ssy[q], rx[u] * ssx[q]);
+      const double c = (dn * ds) * (inv[u] * inv[u]);
+      if (ACC) {
+        two_sum_acc(ax[t], cxa[t], c * rx[u]);
+        two_sum_acc(ay[t], cya[t], c * ry[u]);
+      } else {
+        ax[t] = fma(c, rx[u], ax[t]);
+        ay[t] = fma(c, ry[u], ay[t]);
+      }
+    }
+}
+
 // One workgroup of the pair sum: target tile `tile` (kBlock * T targets)
-// against source chunk `ch` (sources [ch * chunk, (ch + 1) * chunk)).
+// against source chunk `ch` (sources [ch * chunk, (ch + 1) * chunk)).  The
+// plain kernel takes two sources per step for T <= 4 (eight or fewer
+// reciprocals share one hardware reciprocal); the compensated one takes one.
 template <int T, bool ACC>
 __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, const double *__restrict__ xs,
                                                const double *__restrict__ ys, int64_t nn, int64_t chunk,
                                                double *__restrict__ part, int64_t tile, int64_t ch) {
+  constexpr int S = (!ACC && T <= 4) ? 2 : 1;
   const int64_t tile0 = tile * (kBlock * T) + threadIdx.x;
   double xi[T], yi[T], ax[T], ay[T], cxa[T], cya[T];
 #pragma unroll
@@ -172,38 +246,13 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
     cxa[t] = 0.0;
     cya[t] = 0.0;
   }
-  // uniform loop bounds kept in scalar registers
-  const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(ch * chunk));
-  int64_t j1 = j0 + chunk < nn ? j0 + chunk : nn;
-  j1 = __builtin_amdgcn_readfirstlane((int)j1);
-  for (int64_t j = j0; j < j1; ++j) {
-    const double *s = src + 8 * j;  // wave-uniform: scalar loads
-    const double sx = s[0], sy = s[1], sax = s[2], say = s[3], ssx = s[4],
-                 ssy = s[5];
-    double rx[T], ry[T], r2[T], inv[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      rx[t] = xi[t] - sx;
-      ry[t] = yi[t] - sy;
-      // the self pair has r = 0 exactly: clamping rho^2 keeps 1/rho^4 finite
-      // and the pair's factors (r.a)(r.sigma) are exactly zero
-      r2[t] = fmax(fma(ry[t], ry[t], rx[t] * rx[t]), 1e-100);
-    }
-    batch_recip<T>(r2, inv);
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const double dn = fma(ry[t], say, rx[t] * sax);
-      const double ds = fma(ry[t], ssy, rx[t] * ssx);
-      const double c = (dn * ds) * (inv[t] * inv[t]);
-      if (ACC) {
-        two_sum_acc(ax[t], cxa[t], c * rx[t]);
-        two_sum_acc(ay[t], cya[t], c * ry[t]);
-      } else {
-        ax[t] = fma(c, rx[t], ax[t]);
-        ay[t] = fma(c, ry[t], ay[t]);
-      }
-    }
-  }
+  // uniform 32-bit loop bounds kept in scalar registers (node counts are
+  // below 2^31), so the loop test is a scalar compare
+  const int j0 = __builtin_amdgcn_readfirstlane((int)(ch * chunk));
+  const int j1 = __builtin_amdgcn_readfirstlane((int)(ch * chunk + chunk < nn ? ch * chunk + chunk : nn));
+  const int js = j1 > j0 ? j0 + ((j1 - j0) / S) * S : j0;
+  for (int j = j0; j < js; j += S) pair_step<T, S, ACC>(src, j, xi, yi, ax, ay, cxa, cya);
+  for (int j = js; j < j1; ++j) pair_step<T, 1, ACC>(src, j, xi, yi, ax, ay, cxa, cya);
   double *px = part + ch * 4 * nn;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -419,6 +468,44 @@ __global__ void wall_length_kernel(int64_t wall_start, int64_t nn,
 
 size_t MatvecWork::doubles() const { return 0; }
 
+// Workgroups of the plain pair kernel (targets per thread tpt) that the whole
+// device holds at once: occupancy per compute unit times the unit count.
+int64_t resident_pair_blocks(int tpt) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int64_t> cache;
+  int dev = 0;
+  SBIE_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({dev, tpt});
+  if (it != cache.end()) return it->second;
+  const void *fn = nullptr;
+  switch (tpt) {
+    case 1: fn = reinterpret_cast<const void *>(&dlp_pairs<1, false>); break;
+    case 2: fn = reinterpret_cast<const void *>(&dlp_pairs<2, false>); break;
+    case 4: fn = reinterpret_cast<const void *>(&dlp_pairs<4, false>); break;
+    default: fn = reinterpret_cast<const void *>(&dlp_pairs<8, false>); break;
+  }
+  int per_cu = 0, cus = 0;
+  SBIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
+  SBIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t r = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  cache[{dev, tpt}] = r;
+  return r;
+}
+
+// Source chunks for the pair kernel.  All (tile, chunk) workgroups cost the
+// same; with few of them per resident slot the last, partly filled round of
+// workgroups is a large share of the run.  About seven rounds of the
+// device's resident workgroups keep that share small while the partial sums
+// (2 nn doubles per chunk, re-read by the epilogue) stay a few percent of
+// the pair time; chunks hold at least 128 sources.
+int choose_chunks(int64_t nn, int64_t tiles, int tpt) {
+  const int64_t resident = resident_pair_blocks(tpt);
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((nn + 127) / 128, 1024));
+  const int64_t want = (7 * resident + tiles - 1) / tiles;
+  return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
 MatvecWork plan_matvec(const sbie_geom *g) {
   MatvecWork w;
   w.tpt = g_tpt;
@@ -427,11 +514,7 @@ MatvecWork plan_matvec(const sbie_geom *g) {
   if (g_chunks > 0) {
     w.chunks = g_chunks;
   } else {
-    int64_t want = (4096 + tiles - 1) / tiles;
-    int64_t cap = (nn + 127) / 128;
-    if (want > cap) want = cap;
-    if (want < 1) want = 1;
-    w.chunks = (int)want;
+    w.chunks = choose_chunks(nn, tiles, w.tpt);
   }
   if ((int64_t)w.chunks > nn) w.chunks = (int)nn;
   w.pchunks = g->n_pores > 0 ? (int)ceil_div(g->n_pores, kPoreChunk) : 0;
