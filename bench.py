@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--cheb-n", type=int, default=8)
+    ap.add_argument("--cheb-n", type=int, default=6)
     ap.add_argument("--ifmm-precision", type=int, default=0,
                     help="0 = FP64 factor/apply, 1 = FP32 (mixed precision)")
     ap.add_argument("--copy-calibration", action="store_true",

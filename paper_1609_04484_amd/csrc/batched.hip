@@ -1,5 +1,6 @@
 // Variable-size batched dense kernels (double and float instantiations).
 #include <cstring>
+#include <type_traits>
 
 #include "batched.hpp"
 
@@ -32,6 +33,26 @@ void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
   void *d = dev.p + used;
   used += need;
   return d;
+}
+
+void Stager::put_many(const std::vector<std::pair<const void *, size_t>> &parts, std::vector<void *> &dst,
+                      hipStream_t s) {
+  size_t need = 0;
+  for (const auto &p : parts) need += (p.second + 255) & ~size_t(255);
+  if (need > cap) fail(SBIE_OUT_OF_MEMORY, "descriptor batch of %zu bytes exceeds staging", need);
+  if (used + need > cap) {
+    SBIE_HIP(hipStreamSynchronize(s));
+    used = 0;
+  }
+  dst.resize(parts.size());
+  size_t o = used;
+  for (size_t i = 0; i < parts.size(); ++i) {
+    if (parts[i].second) std::memcpy(host + o, parts[i].first, parts[i].second);
+    dst[i] = dev.p + o;
+    o += (parts[i].second + 255) & ~size_t(255);
+  }
+  SBIE_HIP(hipMemcpyAsync(dev.p + used, host + used, o - used, hipMemcpyHostToDevice, s));
+  used = o;
 }
 
 namespace {
@@ -112,16 +133,24 @@ __global__ __launch_bounds__(256) void gemm_tiles(const GemmDesc<T> *__restrict_
 // ----------------------------------------------------------------------------
 // GEMV: one workgroup per descriptor (at most 64 rows)
 // ----------------------------------------------------------------------------
+// The GEMV is bound by how many loads each workgroup keeps in flight: a
+// descriptor (at most 64 rows) gets 16 waves.  Untransposed terms: lane =
+// row, wave w takes columns w, w + 16, ... with four independent chains;
+// transposed terms: wave w takes rows w, w + 16, w + 32, w + 48, lanes
+// stride over the columns.  Partial sums meet in LDS.
+constexpr int kGemvThreads = 1024;
+constexpr int kGemvWaves = kGemvThreads / 64;
+
 template <class T>
-__global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__ descs,
-                                                 const GemvTerm<T> *__restrict__ terms) {
+__global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__restrict__ descs,
+                                                          const GemvTerm<T> *__restrict__ terms) {
   const GemvDesc<T> d = descs[blockIdx.x];
-  __shared__ T part[4][64];
+  __shared__ T part[kGemvWaves][64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  T acc = T(0);        // trans = 0: this thread's partial for row `lane`
-  T accw[16];          // trans = 1: wave-owned rows wv, wv + 4, ...
+  T acc = T(0);        // untransposed: this thread's partial for row `lane`
+  T accw[4];           // transposed: rows wv, wv + 16, wv + 32, wv + 48
 #pragma unroll
-  for (int q = 0; q < 16; ++q) accw[q] = T(0);
+  for (int q = 0; q < 4; ++q) accw[q] = T(0);
   for (int t = d.t0; t < d.t0 + d.nt; ++t) {
     const GemvTerm<T> tm = terms[t];
     if (!tm.trans) {
@@ -129,20 +158,19 @@ __global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__
       if (lane < d.rows) {
         const T *a = tm.A + lane;
         int c = wv;
-        // four independent chains keep several loads in flight
-        for (; c + 12 < tm.cols; c += 16) {
+        for (; c + 3 * kGemvWaves < tm.cols; c += 4 * kGemvWaves) {
           s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
-          s1 = fma(a[(size_t)(c + 4) * tm.lda], tm.x[c + 4], s1);
-          s2 = fma(a[(size_t)(c + 8) * tm.lda], tm.x[c + 8], s2);
-          s3 = fma(a[(size_t)(c + 12) * tm.lda], tm.x[c + 12], s3);
+          s1 = fma(a[(size_t)(c + kGemvWaves) * tm.lda], tm.x[c + kGemvWaves], s1);
+          s2 = fma(a[(size_t)(c + 2 * kGemvWaves) * tm.lda], tm.x[c + 2 * kGemvWaves], s2);
+          s3 = fma(a[(size_t)(c + 3 * kGemvWaves) * tm.lda], tm.x[c + 3 * kGemvWaves], s3);
         }
-        for (; c < tm.cols; c += 4) s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
+        for (; c < tm.cols; c += kGemvWaves) s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
       }
       acc = fma(tm.alpha, (s0 + s1) + (s2 + s3), acc);
     } else {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int r = wv + 4 * q;
+      for (int q = 0; q < 4; ++q) {
+        const int r = wv + kGemvWaves * q;
         if (r >= d.rows) break;
         const T *col = tm.A + (size_t)r * tm.lda;
         T s = T(0);
@@ -156,14 +184,17 @@ __global__ __launch_bounds__(256) void gemv_desc(const GemvDesc<T> *__restrict__
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = wv + 4 * q;
+    for (int q = 0; q < 4; ++q) {
+      const int r = wv + kGemvWaves * q;
       if (r < d.rows) part[wv][r] += accw[q];
     }
   }
   __syncthreads();
   if (tid < d.rows) {
-    const T v = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    T v = T(0);
+#pragma unroll
+    for (int w = 0; w < kGemvWaves; w += 4)
+      v += (part[w][tid] + part[w + 1][tid]) + (part[w + 2][tid] + part[w + 3][tid]);
     T *y = d.y + tid;
     if (d.beta != T(0)) {
       const T base = d.y0 ? d.y0[tid] : *y;
@@ -393,18 +424,26 @@ __global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ pt
 // ----------------------------------------------------------------------------
 // Truncated pivoted Gram-Schmidt (rank-revealing), one workgroup per problem
 // ----------------------------------------------------------------------------
+// One workgroup of kPgsThreads per candidate block: the candidates' residual
+// norms live in LDS; each accepted column is re-orthogonalised twice against
+// the basis, normalised, appended, and projected out of every candidate that
+// can still be chosen.  Reductions go through wave shuffles, then across the
+// 16 waves in LDS.
+constexpr int kPgsThreads = 1024;
+constexpr int kPgsWaves = kPgsThreads / 64;
+
 template <class T>
-__global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__ descs) {
+__global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__restrict__ descs) {
   extern __shared__ unsigned char shraw[];
   const PgsDesc<T> d = descs[blockIdx.x];
   double *norms = reinterpret_cast<double *>(shraw);   // c
   double *dots = norms + d.c;                           // rmax
   T *q = reinterpret_cast<T *>(dots + d.rmax);          // m
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
+  __shared__ double red_v[kPgsWaves];
+  __shared__ int red_i[kPgsWaves];
   __shared__ int s_stop;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int j = wv; j < d.c; j += 4) {
+  for (int j = wv; j < d.c; j += kPgsWaves) {
     const T *col = d.R + (size_t)j * d.ldr;
     double s = 0.0;
     for (int i = lane; i < d.m; i += 64) s = fma((double)col[i], (double)col[i], s);
@@ -417,33 +456,29 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
   int guard = 0;
   while (d.r0 + k < d.rmax && guard < d.c + d.rmax) {
     ++guard;
+    // pivot: the candidate of largest residual norm (lowest index on ties)
     double best = -1.0;
     int bi = 0;
-    for (int j = tid; j < d.c; j += 256)
+    for (int j = tid; j < d.c; j += kPgsThreads)
       if (norms[j] > best) { best = norms[j]; bi = j; }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double ov = red_v[tid + s];
-        const int oi = red_i[tid + s];
-        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
-          red_v[tid] = ov;
-          red_i[tid] = oi;
-        }
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_down(best, o, 64);
+      const int oi = __shfl_down(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
     }
-    const double vmax = red_v[0];
-    const int p = red_i[0];
+    if (lane == 0) { red_v[wv] = best; red_i[wv] = bi; }
+    __syncthreads();
+    double vmax = red_v[0];
+    int p = red_i[0];
+    for (int w = 1; w < kPgsWaves; ++w)
+      if (red_v[w] > vmax || (red_v[w] == vmax && red_i[w] < p)) { vmax = red_v[w]; p = red_i[w]; }
     __syncthreads();
     if (!(vmax > tol2)) break;
-    for (int i = tid; i < d.m; i += 256) q[i] = d.R[i + (size_t)p * d.ldr];
+    for (int i = tid; i < d.m; i += kPgsThreads) q[i] = d.R[i + (size_t)p * d.ldr];
     __syncthreads();
     const int rc = d.r0 + k;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int col = wv; col < rc; col += 4) {
+      for (int col = wv; col < rc; col += kPgsWaves) {
         const T *w = d.W + (size_t)col * d.ldw;
         double s = 0.0;
         for (int i = lane; i < d.m; i += 64) s = fma((double)w[i], (double)q[i], s);
@@ -451,23 +486,20 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
         if (lane == 0) dots[col] = s;
       }
       __syncthreads();
-      for (int i = tid; i < d.m; i += 256) {
+      for (int i = tid; i < d.m; i += kPgsThreads) {
         double v = (double)q[i];
         for (int col = 0; col < rc; ++col) v = fma(-(double)d.W[i + (size_t)col * d.ldw], dots[col], v);
         q[i] = (T)v;
       }
       __syncthreads();
     }
-    double s = 0.0;
-    for (int i = tid; i < d.m; i += 256) s = fma((double)q[i], (double)q[i], s);
-    red_v[tid] = s;
+    double sq = 0.0;
+    for (int i = tid; i < d.m; i += kPgsThreads) sq = fma((double)q[i], (double)q[i], sq);
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
+    if (lane == 0) red_v[wv] = sq;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red_v[tid] += red_v[tid + st];
-      __syncthreads();
-    }
-    const double nq = red_v[0];
-    __syncthreads();
+    double nq = 0.0;
+    for (int w = 0; w < kPgsWaves; ++w) nq += red_v[w];
     if (tid == 0) s_stop = (nq <= 1e-4 * vmax || !(nq > 0.0)) ? 1 : 0;
     __syncthreads();
     if (s_stop) {
@@ -478,14 +510,14 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
     }
     const double inv = 1.0 / sqrt(nq);
     T *wn = d.W + (size_t)rc * d.ldw;
-    for (int i = tid; i < d.m; i += 256) {
+    for (int i = tid; i < d.m; i += kPgsThreads) {
       const T v = (T)((double)q[i] * inv);
       q[i] = v;
       wn[i] = v;
     }
     __syncthreads();
     ++k;
-    for (int j = wv; j < d.c; j += 4) {
+    for (int j = wv; j < d.c; j += kPgsWaves) {
       // a column already below the tolerance can never be chosen again and
       // its residual norm only decreases: leave it alone
       if (!(norms[j] > tol2)) continue;
@@ -494,14 +526,14 @@ __global__ __launch_bounds__(256) void pgs_kernel(const PgsDesc<T> *__restrict__
       for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);
       for (int o = 32; o > 0; o >>= 1) dt += __shfl_down(dt, o, 64);
       dt = __shfl(dt, 0, 64);
-      double sq = 0.0;
+      double sq2 = 0.0;
       for (int i = lane; i < d.m; i += 64) {
         const T v = (T)((double)col[i] - dt * (double)q[i]);
         col[i] = v;
-        sq = fma((double)v, (double)v, sq);
+        sq2 = fma((double)v, (double)v, sq2);
       }
-      for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
-      if (lane == 0) norms[j] = sq;
+      for (int o = 32; o > 0; o >>= 1) sq2 += __shfl_down(sq2, o, 64);
+      if (lane == 0) norms[j] = sq2;
     }
     __syncthreads();
   }
@@ -594,6 +626,158 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const PanelDesc<T> *__
   }
 }
 
+// Same result for panels of at most kPanelRegRows rows, with two barriers
+// per column instead of a dozen: each of 256 threads keeps up to three rows
+// of the panel in registers (row i belongs to thread i % 256, slot i / 256).
+// A step takes a wave-shuffle argmax, one barrier to combine the four waves,
+// then the owners of rows t and p post both rows in LDS and, after the
+// second barrier, every thread reads the pivot row from there and updates
+// its rows.  LDS buffers alternate between steps, so the next step's posts
+// cannot overwrite what a slower wave still reads.  Finally the swaps are
+// applied to A as one permutation of the touched rows, one column per thread,
+// all loads of a column in flight together.
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+constexpr int kPanelThreads = 256;
+constexpr int kPanelSlots = 3;
+constexpr int kPanelRegRows = kPanelThreads * kPanelSlots;
+
+template <class T>
+__global__ __launch_bounds__(kPanelThreads) void panel_pivot_reg_kernel(const PanelDesc<T> *__restrict__ descs) {
+  constexpr int PB = 32;
+  constexpr int NW = kPanelThreads / 64;
+  const PanelDesc<T> d = descs[blockIdx.x];
+  __shared__ double w_v[2][NW];
+  __shared__ int w_i[2][NW];
+  __shared__ T prow[2][PB], xrow[2][PB];
+  __shared__ int u_pos[2 * PB], u_src[2 * PB];
+  __shared__ int s_nu;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int h = d.n - d.k0, pb = d.pb;
+  T row[kPanelSlots][PB];
+#pragma unroll
+  for (int q = 0; q < kPanelSlots; ++q) {
+    const int r = tid + kPanelThreads * q;
+#pragma unroll
+    for (int c = 0; c < PB; ++c)
+      row[q][c] = (r < h && c < pb) ? d.A[(d.k0 + r) + (size_t)(d.k0 + c) * d.n] : T(0);
+  }
+  // one step per column, expanded at compile time (static_for) so that every
+  // column index is a constant and the rows stay in registers
+  bool failed = false;
+  static_for<0, PB>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    if (failed || t >= pb) return;
+    const int par = t & 1;
+    // argmax of |row[t]| over rows r >= t (lowest row on ties)
+    double v = -1.0;
+    int bi = t;
+#pragma unroll
+    for (int q = 0; q < kPanelSlots; ++q) {
+      const int r = tid + kPanelThreads * q;
+      const double a = fabs((double)row[q][t]);
+      if (r >= t && r < h && a > v) { v = a; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_down(v, o, 64);
+      const int oi = __shfl_down(bi, o, 64);
+      if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+    }
+    if (lane == 0) { w_v[par][wv] = v; w_i[par][wv] = bi; }
+    __syncthreads();
+    double pv = w_v[par][0];
+    int p = w_i[par][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (w_v[par][w] > pv || (w_v[par][w] == pv && w_i[par][w] < p)) { pv = w_v[par][w]; p = w_i[par][w]; }
+    if (!(pv > 0.0) || !isfinite(pv)) {
+      if (tid == 0) *d.info = d.k0 + t + 1;
+      failed = true;
+      return;
+    }
+    if (tid == 0) d.ipiv[d.k0 + t] = d.k0 + p;
+    // owners post rows p (the pivot) and t
+#pragma unroll
+    for (int q = 0; q < kPanelSlots; ++q) {
+      const int r = tid + kPanelThreads * q;
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) prow[par][c] = row[q][c];
+      }
+      if (r == t) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) xrow[par][c] = row[q][c];
+      }
+    }
+    __syncthreads();
+    // rows t and p trade places; every row below t is updated
+#pragma unroll
+    for (int q = 0; q < kPanelSlots; ++q) {
+      const int r = tid + kPanelThreads * q;
+      if (r == t) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) row[q][c] = prow[par][c];
+      } else if (r == p) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) row[q][c] = xrow[par][c];
+      }
+      if (r > t && r < h) {
+        const T l = row[q][t] / prow[par][t];
+        row[q][t] = l;
+#pragma unroll
+        for (int c = t + 1; c < PB; ++c) row[q][c] = fma(-l, prow[par][c], row[q][c]);
+      }
+    }
+  });
+  if (failed) return;
+  // the combined permutation of the touched rows, from replaying the swaps
+  // on row labels
+  __syncthreads();
+  if (tid == 0) {
+    int nu = 0;
+    auto slot = [&](int r) {
+      for (int i = 0; i < nu; ++i)
+        if (u_pos[i] == r) return i;
+      u_pos[nu] = r;
+      u_src[nu] = r;
+      return nu++;
+    };
+    for (int t = 0; t < pb; ++t) {
+      const int k = d.k0 + t, p = d.ipiv[k];
+      if (p == k) continue;
+      const int a = slot(k), b = slot(p);
+      const int x = u_src[a];
+      u_src[a] = u_src[b];
+      u_src[b] = x;
+    }
+    s_nu = nu;
+  }
+  __syncthreads();
+  const int nu = s_nu;
+  if (nu == 0) return;
+  // blocks of 64 columns staged through LDS: all touched values of the block
+  // are loaded before any is stored
+  __shared__ T stage[2 * PB][64];
+  for (int c0 = 0; c0 < d.n; c0 += 64) {
+    for (int e = tid; e < nu * 64; e += kPanelThreads) {
+      const int i = e >> 6, c = c0 + (e & 63);
+      if (c < d.n) stage[i][e & 63] = d.A[u_src[i] + (size_t)c * d.n];
+    }
+    __syncthreads();
+    for (int e = tid; e < nu * 64; e += kPanelThreads) {
+      const int i = e >> 6, c = c0 + (e & 63);
+      if (c < d.n) d.A[u_pos[i] + (size_t)c * d.n] = stage[i][e & 63];
+    }
+    __syncthreads();
+  }
+}
+
 // Undo the row interchanges as column interchanges of the inverse.
 template <class T>
 __global__ __launch_bounds__(256) void unswap_columns_kernel(T *const *__restrict__ ptrs,
@@ -647,23 +831,94 @@ __global__ void convert_kernel(const A *src, B *dst, size_t n) {
 
 }  // namespace
 
+// C = beta C + sum of P partial products (m x n each, leading dimension m)
+template <class T>
+__global__ void splitk_reduce(const T *__restrict__ part, int P, int m, int n, T *__restrict__ C, int ldc,
+                              T beta) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  T v = T(0);
+  for (int p = 0; p < P; ++p) v += part[(int64_t)p * m * n + e];
+  T *o = C + r + (size_t)c * ldc;
+  *o = beta != T(0) ? fma(beta, *o, v) : v;
+}
+
 template <class T>
 void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) {
+  // A batch with few output tiles but a long inner dimension would leave
+  // most compute units idle while a handful of workgroups walk the whole k
+  // range: such products are split along k into partial products (written
+  // to scratch) that one more kernel sums.
+  constexpr int64_t kWantTiles = 1024, kMinSlice = 512;
+  int64_t total = 0;
+  for (const auto &g : d)
+    if (g.m > 0 && g.n > 0) total += (int64_t)((g.m + 63) / 64) * ((g.n + 63) / 64);
+  if (total == 0) return;
   std::vector<GemmDesc<T>> keep;
   std::vector<int2> tiles;
+  struct Split { GemmDesc<T> g; int P; size_t off; };
+  std::vector<Split> splits;
+  size_t scratch_elems = 0;
+  std::vector<GemmDesc<T>> parts;
   for (const auto &g : d) {
     if (g.m <= 0 || g.n <= 0) continue;
+    const int64_t nt = (int64_t)((g.m + 63) / 64) * ((g.n + 63) / 64);
+    int P = 1;
+    if (total < kWantTiles / 2 && g.k >= 4 * kMinSlice)
+      P = (int)std::max<int64_t>(1, std::min<int64_t>(g.k / kMinSlice, kWantTiles / total));
+    if (P <= 1) {
+      parts.push_back(g);
+      continue;
+    }
+    splits.push_back({g, P, scratch_elems});
+    scratch_elems += (size_t)P * g.m * g.n;
+    (void)nt;
+  }
+  StreamBuf<T> scratch(scratch_elems, s);
+  for (const auto &sp : splits) {
+    const GemmDesc<T> &g = sp.g;
+    const int slice = (g.k + sp.P - 1) / sp.P;
+    for (int p = 0; p < sp.P; ++p) {
+      const int k0 = p * slice, kk = std::min(slice, g.k - k0);
+      if (kk <= 0) {
+        // an empty slice still owns its partial buffer: write zeros
+        GemmDesc<T> z = g;
+        z.k = 0;
+        z.C = scratch.p + sp.off + (size_t)p * g.m * g.n;
+        z.ldc = g.m;
+        z.beta = T(0);
+        parts.push_back(z);
+        continue;
+      }
+      GemmDesc<T> q = g;
+      q.k = kk;
+      q.A = g.ta ? g.A + k0 : g.A + (size_t)k0 * g.lda;
+      q.B = g.tb ? g.B + (size_t)k0 * g.ldb : g.B + k0;
+      q.C = scratch.p + sp.off + (size_t)p * g.m * g.n;
+      q.ldc = g.m;
+      q.beta = T(0);
+      parts.push_back(q);
+    }
+  }
+  for (const auto &g : parts) {
     const int id = (int)keep.size();
     keep.push_back(g);
     const int nt = ((g.m + 63) / 64) * ((g.n + 63) / 64);
     for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(id, t));
   }
-  if (tiles.empty()) return;
-  auto *dd = (const GemmDesc<T> *)st.put(keep.data(), keep.size() * sizeof(GemmDesc<T>), s);
   for (size_t t0 = 0; t0 < tiles.size(); t0 += 1u << 20) {
     const size_t nt = std::min(tiles.size() - t0, size_t(1) << 20);
-    auto *td = (const int2 *)st.put(tiles.data() + t0, nt * sizeof(int2), s);
-    gemm_tiles<T><<<(unsigned)nt, 256, 0, s>>>(dd, td);
+    std::vector<void *> dev;
+    st.put_many({{keep.data(), keep.size() * sizeof(GemmDesc<T>)}, {tiles.data() + t0, nt * sizeof(int2)}},
+                dev, s);
+    gemm_tiles<T><<<(unsigned)nt, 256, 0, s>>>((const GemmDesc<T> *)dev[0], (const int2 *)dev[1]);
+    SBIE_LAUNCH_CHECK();
+  }
+  for (const auto &sp : splits) {
+    const int64_t e = (int64_t)sp.g.m * sp.g.n;
+    splitk_reduce<T><<<ceil_div(e, 256), 256, 0, s>>>(scratch.p + sp.off, sp.P, sp.g.m, sp.g.n, sp.g.C,
+                                                     sp.g.ldc, sp.g.beta);
     SBIE_LAUNCH_CHECK();
   }
 }
@@ -671,7 +926,7 @@ void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) 
 template <class T>
 void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T> *t, int nd, int, hipStream_t s) {
   if (nd == 0) return;
-  gemv_desc<T><<<nd, 256, 0, s>>>(d, t);
+  gemv_desc<T><<<nd, kGemvThreads, 0, s>>>(d, t);
   SBIE_LAUNCH_CHECK();
 }
 
@@ -679,9 +934,9 @@ template <class T>
 void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<T>> &t,
                   Stager &st, hipStream_t s) {
   if (d.empty()) return;
-  auto *tt = (const GemvTerm<T> *)st.put(t.data(), std::max<size_t>(1, t.size()) * sizeof(GemvTerm<T>), s);
-  auto *dd = (const GemvDesc<T> *)st.put(d.data(), d.size() * sizeof(GemvDesc<T>), s);
-  gemv_launch<T>(dd, tt, (int)d.size(), 64, s);
+  std::vector<void *> dev;
+  st.put_many({{t.data(), t.size() * sizeof(GemvTerm<T>)}, {d.data(), d.size() * sizeof(GemvDesc<T>)}}, dev, s);
+  gemv_launch<T>((const GemvDesc<T> *)dev[1], (const GemvTerm<T> *)dev[0], (int)d.size(), 64, s);
 }
 
 template <class T>
@@ -709,6 +964,104 @@ void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s) 
   }
 }
 
+// Gauss-Jordan inverse with partial pivoting of one matrix of order n <=
+// NMAX per wave (64 threads), in place: lane i keeps row i in registers, the
+// column loop is expanded at compile time, so no step needs a barrier.  The
+// pivot is a shuffle argmax; rows k and p trade places and the scaled pivot
+// row is broadcast through LDS.  Same operations as gj_small_kernel; the
+// column interchanges are undone through LDS on the way out.
+template <class T, int NMAX>
+__global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs, const int *__restrict__ ns,
+                                                     int32_t *__restrict__ info) {
+  __shared__ T xk[NMAX], xp[NMAX], prow[NMAX];
+  __shared__ T out[NMAX][NMAX + 1];
+  __shared__ int ipv[NMAX], lab[NMAX];
+  const int b = blockIdx.x;
+  const int n = ns[b];
+  T *A = ptrs[b];
+  const int i = threadIdx.x;
+  T r[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? A[i + (size_t)c * n] : T(0);
+  bool failed = false;
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (failed || k >= n) return;
+    double v = (i >= k && i < n) ? fabs((double)r[k]) : -1.0;
+    int bi = i;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bi);
+    if (!(v > 0.0) || !isfinite(v)) {
+      if (i == 0) info[b] = k + 1;
+      failed = true;
+      return;
+    }
+    if (i == 0) ipv[k] = p;
+    if (p != k) {
+      if (i == k) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) xk[c] = r[c];
+      }
+      if (i == p) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) xp[c] = r[c];
+      }
+      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the rows are in LDS
+      __builtin_amdgcn_wave_barrier();
+      if (i == k) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) r[c] = xp[c];
+      }
+      if (i == p) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) r[c] = xk[c];
+      }
+    }
+    // scaled pivot row: row k with M[k][k] replaced by 1, divided by the pivot
+    if (i == k) {
+      const T inv = T(1) / r[k];
+      r[k] = T(1);
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) {
+        r[c] *= inv;
+        prow[c] = r[c];
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    if (i != k && i < n) {
+      const T f = r[k];
+      r[k] = T(0);
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[c], r[c]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  });
+  if (failed) return;
+  // column interchanges in reverse order, as one permutation of labels
+  if (i == 0) {
+    for (int c = 0; c < n; ++c) lab[c] = c;
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = ipv[k];
+      const int t = lab[k];
+      lab[k] = lab[p];
+      lab[p] = t;
+    }
+  }
+  if (i < NMAX) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) out[i][c] = r[c];
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+  if (i < n)
+    for (int c = 0; c < n; ++c) A[i + (size_t)c * n] = out[i][lab[c]];
+}
+
 template <class T>
 void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                      int32_t *info_dev, Stager &st, hipStream_t s) {
@@ -717,10 +1070,14 @@ void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
   for (int n : ns) mx = std::max(mx, n);
   const size_t shmem = 2 * mx * sizeof(T) + mx * sizeof(int);
   if (shmem > 56 * 1024) fail(SBIE_UNSUPPORTED, "dense block of size %d too large to invert", mx);
-  auto *pd = (T *const *)st.put(ptrs.data(), ptrs.size() * sizeof(T *), s);
-  auto *nd = (const int *)st.put(ns.data(), ns.size() * sizeof(int), s);
-  if (mx <= 64)
-    gj_small_kernel<T><<<(unsigned)ptrs.size(), 256, 0, s>>>(pd, nd, info_dev);
+  std::vector<void *> dev;
+  st.put_many({{ptrs.data(), ptrs.size() * sizeof(T *)}, {ns.data(), ns.size() * sizeof(int)}}, dev, s);
+  auto *pd = (T *const *)dev[0];
+  auto *nd = (const int *)dev[1];
+  if (mx <= 32)
+    gj_wave_kernel<T, 32><<<(unsigned)ptrs.size(), 64, 0, s>>>(pd, nd, info_dev);
+  else if (mx <= 64)
+    gj_wave_kernel<T, 64><<<(unsigned)ptrs.size(), 64, 0, s>>>(pd, nd, info_dev);
   else
     gj_kernel<T><<<(unsigned)ptrs.size(), 256, shmem, s>>>(pd, nd, info_dev);
   SBIE_LAUNCH_CHECK();
@@ -773,6 +1130,53 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       poff[b] = P.p + (size_t)b * nb * nb;
       ipv[b] = piv.p + (size_t)b * maxn;
     }
+    // Every panel step's descriptors are known up front: they are packed
+    // into one host blob and uploaded in a single transfer, and the steps
+    // then launch back to back with no host work in between.
+    std::vector<char> blob;
+    auto add = [&](const void *src, size_t bytes) {
+      const size_t o = (blob.size() + 255) & ~size_t(255);
+      blob.resize(o + std::max<size_t>(bytes, 1));
+      if (bytes) std::memcpy(blob.data() + o, src, bytes);
+      return o;
+    };
+    struct GemmPrep { size_t d = 0, t = 0; unsigned nt = 0; };
+    struct CopyPrep { size_t d = 0; int n = 0, max_cols = 0; };
+    auto prep_gemm = [&](const std::vector<GemmDesc<T>> &g) {
+      std::vector<GemmDesc<T>> keep;
+      std::vector<int2> tl;
+      for (const auto &q : g) {
+        if (q.m <= 0 || q.n <= 0) continue;
+        const int id = (int)keep.size();
+        keep.push_back(q);
+        const int nt = ((q.m + 63) / 64) * ((q.n + 63) / 64);
+        for (int t = 0; t < nt; ++t) tl.push_back(make_int2(id, t));
+      }
+      GemmPrep r;
+      r.d = add(keep.data(), keep.size() * sizeof(GemmDesc<T>));
+      r.t = add(tl.data(), tl.size() * sizeof(int2));
+      r.nt = (unsigned)tl.size();
+      return r;
+    };
+    auto prep_copy = [&](const std::vector<CopyDesc<T>> &c) {
+      std::vector<CopyDesc<T>> keep;
+      CopyPrep r;
+      for (const auto &q : c)
+        if (q.rows > 0 && q.cols > 0) {
+          keep.push_back(q);
+          r.max_cols = std::max(r.max_cols, q.cols);
+        }
+      r.d = add(keep.data(), keep.size() * sizeof(CopyDesc<T>));
+      r.n = (int)keep.size();
+      return r;
+    };
+    struct Step {
+      size_t pd = 0, pp = 0, pn = 0;
+      int npd = 0, hmax = 0, pmax = 0;
+      CopyPrep cP, cC, cZ, cRz, cRow, cPin;
+      GemmPrep gR, gUpd, gCol;
+    };
+    std::vector<Step> steps;
     for (int it = 0; it < npan; ++it) {
       const int k0 = it * nb;
       std::vector<PanelDesc<T>> pd;
@@ -800,23 +1204,68 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         cPin.push_back({poff[b], pb, A + k0 + (size_t)k0 * n, n, pb, pb, 0, 0, T(1)});
       }
       if (pd.empty()) break;
-      auto *dd = (const PanelDesc<T> *)st.put(pd.data(), pd.size() * sizeof(PanelDesc<T>), s);
-      panel_pivot_kernel<T><<<(unsigned)pd.size(), 256, 0, s>>>(dd);   // choose rows, swap
-      SBIE_LAUNCH_CHECK();
-      copy_batched<T>(cP, st, s);                                      // P = A_pp
-      inverse_batched<T>(pp, pn, info_tile + (size_t)it * nbm, st, s);  // P = A_pp^-1
-      copy_batched<T>(cC, st, s);                                      // C = A[:, p]
-      copy_batched<T>(cZ, st, s);                                      // C[p, :] = 0
-      gemm_batched<T>(gR, st, s);                                      // R = P A[p, :]
-      copy_batched<T>(cRz, st, s);                                     // R[:, p] = 0
-      gemm_batched<T>(gUpd, st, s);                                    // A -= C R
-      copy_batched<T>(cRow, st, s);                                    // A[p, :] = R
-      gemm_batched<T>(gCol, st, s);                                    // A[:, p] = -C P
-      copy_batched<T>(cPin, st, s);                                    // A_pp = P
+      Step st_;
+      st_.npd = (int)pd.size();
+      for (const auto &q : pd) st_.hmax = std::max(st_.hmax, q.n - q.k0);
+      for (int q : pn) st_.pmax = std::max(st_.pmax, q);
+      st_.pd = add(pd.data(), pd.size() * sizeof(PanelDesc<T>));
+      st_.pp = add(pp.data(), pp.size() * sizeof(T *));
+      st_.pn = add(pn.data(), pn.size() * sizeof(int));
+      st_.cP = prep_copy(cP);
+      st_.cC = prep_copy(cC);
+      st_.cZ = prep_copy(cZ);
+      st_.gR = prep_gemm(gR);
+      st_.cRz = prep_copy(cRz);
+      st_.gUpd = prep_gemm(gUpd);
+      st_.cRow = prep_copy(cRow);
+      st_.gCol = prep_gemm(gCol);
+      st_.cPin = prep_copy(cPin);
+      steps.push_back(st_);
     }
-    auto *pd_ = (T *const *)st.put(bp.data(), bp.size() * sizeof(T *), s);
-    auto *nd_ = (const int *)st.put(bn.data(), bn.size() * sizeof(int), s);
-    auto *id_ = (int *const *)st.put(ipv.data(), ipv.size() * sizeof(int *), s);
+    char *db = (char *)st.put(blob.data(), blob.size(), s);
+    auto copy_step = [&](const CopyPrep &c) {
+      copy_launch<T>((const CopyDesc<T> *)(db + c.d), c.n, c.max_cols, s);
+    };
+    auto gemm_step = [&](const GemmPrep &g) {
+      if (g.nt == 0) return;
+      gemm_tiles<T><<<g.nt, 256, 0, s>>>((const GemmDesc<T> *)(db + g.d), (const int2 *)(db + g.t));
+      SBIE_LAUNCH_CHECK();
+    };
+    for (size_t it = 0; it < steps.size(); ++it) {
+      const Step &q = steps[it];
+      const auto *dd = (const PanelDesc<T> *)(db + q.pd);
+      if (q.hmax <= kPanelRegRows && kPanel <= 32)
+        panel_pivot_reg_kernel<T><<<(unsigned)q.npd, kPanelThreads, 0, s>>>(dd);   // choose rows, swap
+      else
+        panel_pivot_kernel<T><<<(unsigned)q.npd, 256, 0, s>>>(dd);
+      SBIE_LAUNCH_CHECK();
+      copy_step(q.cP);                                                  // P = A_pp
+      {                                                                 // P = A_pp^-1
+        T *const *pp_ = (T *const *)(db + q.pp);
+        const int *pn_ = (const int *)(db + q.pn);
+        int32_t *inf = info_tile + it * nbm;
+        if (q.pmax <= 32)
+          gj_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf);
+        else
+          gj_wave_kernel<T, 64><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf);
+        SBIE_LAUNCH_CHECK();
+      }
+      copy_step(q.cC);                                                  // C = A[:, p]
+      copy_step(q.cZ);                                                  // C[p, :] = 0
+      gemm_step(q.gR);                                                  // R = P A[p, :]
+      copy_step(q.cRz);                                                 // R[:, p] = 0
+      gemm_step(q.gUpd);                                                // A -= C R
+      copy_step(q.cRow);                                                // A[p, :] = R
+      gemm_step(q.gCol);                                                // A[:, p] = -C P
+      copy_step(q.cPin);                                                // A_pp = P
+    }
+    std::vector<void *> dev;
+    st.put_many({{bp.data(), bp.size() * sizeof(T *)}, {bn.data(), bn.size() * sizeof(int)},
+                 {ipv.data(), ipv.size() * sizeof(int *)}},
+                dev, s);
+    auto *pd_ = (T *const *)dev[0];
+    auto *nd_ = (const int *)dev[1];
+    auto *id_ = (int *const *)dev[2];
     unswap_columns_kernel<T><<<nbm, 256, 0, s>>>(pd_, nd_, id_);
     SBIE_LAUNCH_CHECK();
   }
@@ -847,6 +1296,34 @@ void norms_batched(const std::vector<NormDesc<T>> &d, double *out_dev, Stager &s
   SBIE_LAUNCH_CHECK();
 }
 
+// Every column of every block to unit norm: blockIdx.x = block, blockIdx.y =
+// column (beyond a block's width: nothing to do).
+template <class T>
+__global__ __launch_bounds__(256) void normalize_cols_desc(const NormDesc<T> *__restrict__ descs) {
+  const NormDesc<T> d = descs[blockIdx.x];
+  if ((int)blockIdx.y >= d.cols) return;
+  T *col = const_cast<T *>(d.A) + (size_t)blockIdx.y * d.lda;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < d.rows; r += 256) s = fma((double)col[r], (double)col[r], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double nrm = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+  const T scale = nrm > 0.0 ? T(1.0 / nrm) : T(0);
+  for (int r = threadIdx.x; r < d.rows; r += 256) col[r] *= scale;
+}
+
+template <class T>
+void normalize_batched(const std::vector<NormDesc<T>> &d, Stager &st, hipStream_t s) {
+  int mc = 0;
+  for (const auto &q : d) mc = std::max(mc, q.rows > 0 ? q.cols : 0);
+  if (d.empty() || mc == 0) return;
+  auto *dd = (const NormDesc<T> *)st.put(d.data(), d.size() * sizeof(NormDesc<T>), s);
+  normalize_cols_desc<T><<<dim3((unsigned)d.size(), (unsigned)mc), 256, 0, s>>>(dd);
+  SBIE_LAUNCH_CHECK();
+}
+
 template <class T>
 void normalize_columns(T *A, int lda, int rows, int cols, hipStream_t s) {
   if (rows == 0 || cols == 0) return;
@@ -866,7 +1343,7 @@ void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s) {
   if (shmem > 60 * 1024)
     fail(SBIE_UNSUPPORTED, "rank-revealing step too large (%zu bytes of LDS)", shmem);
   auto *dd = (const PgsDesc<T> *)st.put(d.data(), d.size() * sizeof(PgsDesc<T>), s);
-  pgs_kernel<T><<<(unsigned)d.size(), 256, shmem, s>>>(dd);
+  pgs_kernel<T><<<(unsigned)d.size(), kPgsThreads, shmem, s>>>(dd);
   SBIE_LAUNCH_CHECK();
 }
 
@@ -907,6 +1384,7 @@ void convert(const A *src, B *dst, size_t n, hipStream_t s) {
   template void norms_batched<T>(const std::vector<NormDesc<T>> &, double *, Stager &,   \
                                  hipStream_t);                                           \
   template void normalize_columns<T>(T *, int, int, int, hipStream_t);                   \
+  template void normalize_batched<T>(const std::vector<NormDesc<T>> &, Stager &, hipStream_t); \
   template void pgs_batched<T>(const std::vector<PgsDesc<T>> &, Stager &, hipStream_t);  \
   template void gaussian_fill<T>(T *, size_t, uint64_t, hipStream_t);                   \
   template void fill_value<T>(T *, size_t, T, hipStream_t);

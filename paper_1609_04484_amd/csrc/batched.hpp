@@ -64,6 +64,10 @@ struct Stager {
   Stager &operator=(const Stager &) = delete;
   // copy bytes to the device ring (stream-ordered); returns the device address
   void *put(const void *src, size_t bytes, hipStream_t s);
+  // several host arrays in one transfer: dst[i] receives the device address
+  // of part i (each part 256-byte aligned)
+  void put_many(const std::vector<std::pair<const void *, size_t>> &parts, std::vector<void *> &dst,
+                hipStream_t s);
   void reset() { used = 0; }
 };
 
@@ -107,6 +111,9 @@ void norms_batched(const std::vector<NormDesc<T>> &d, double *out_dev, Stager &s
 // Scale each column of blocks to unit norm (zero columns left as zero).
 template <class T>
 void normalize_columns(T *A, int lda, int rows, int cols, hipStream_t s);
+// Same for many blocks (A, lda, rows, cols) in one launch.
+template <class T>
+void normalize_batched(const std::vector<NormDesc<T>> &d, Stager &st, hipStream_t s);
 
 // Truncated pivoted Gram-Schmidt: R (m x c) holds candidate columns already
 // projected against W[:, :r0]; new orthonormal columns (residual column norm

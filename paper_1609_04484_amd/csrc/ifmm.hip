@@ -675,16 +675,18 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   std::vector<T *> phi(nleaf), psi(nleaf), gvec(nleaf), hvec(nleaf);
   {
     std::vector<ChebBox> cb(nleaf);
+    std::vector<CopyDesc<T>> zero;   // alpha = 0 without accumulation: a fill
     for (int b = 0; b < nleaf; ++b) {
       phi[b] = level_arena->get<T>((size_t)m[b] * 2 * n2);
       psi[b] = level_arena->get<T>((size_t)m[b] * 7 * n2);
       gvec[b] = level_arena->get<T>(m[b]);
       hvec[b] = level_arena->get<T>(m[b]);
-      fill_value<T>(phi[b], (size_t)m[b] * 2 * n2, T(0), s);
-      fill_value<T>(psi[b], (size_t)m[b] * 7 * n2, T(0), s);
+      zero.push_back({nullptr, 1, phi[b], m[b], m[b], 2 * n2, 0, 0, T(0)});
+      zero.push_back({nullptr, 1, psi[b], m[b], m[b], 7 * n2, 0, 0, T(0)});
       cb[b] = ChebBox{leaf_dofs_all.p + dof_off[b], m[b], leaf.cx[b], leaf.cy[b], leaf.h,
                       phi[b], psi[b], gvec[b], hvec[b]};
     }
+    copy_batched<T>(zero, st, s);
     auto *dd = (const ChebBox *)st.put(cb.data(), cb.size() * sizeof(ChebBox), s);
     cheb_leaf_kernel<T><<<nleaf, 64, 0, s>>>(dd, gv, cn);
     SBIE_LAUNCH_CHECK();
@@ -792,7 +794,11 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         cd.push_back({hvec[b], m[b], cand[b] + (size_t)m[b] * (ru + rv + 1), m[b], m[b], 1, 0, 0, T(1)});
       }
       copy_batched<T>(cd, st, s);
-      for (int b = 0; b < nb; ++b) normalize_columns<T>(cand[b], m[b], m[b], ru + rv + 2, s);
+      {
+        std::vector<NormDesc<T>> nd;
+        for (int b = 0; b < nb; ++b) nd.push_back({cand[b], m[b], m[b], ru + rv + 2});
+        normalize_batched<T>(nd, st, s);
+      }
       std::vector<PgsDesc<T>> pd;
       for (int b = 0; b < nb; ++b)
         pd.push_back({cand[b], m[b], m[b], ru + rv + 2, W[b], m[b], 0, m[b], eps, counts.p + b});
