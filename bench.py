@@ -60,7 +60,7 @@ def main():
                          "all: IFMM in FP64 and in FP32, and block-diagonal")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
-    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--eps", type=float, default=5e-5)
     ap.add_argument("--cheb-n", type=int, default=6)
     ap.add_argument("--ifmm-precision", type=int, default=0,
                     help="0 = FP64 factor/apply, 1 = FP32 (mixed precision)")

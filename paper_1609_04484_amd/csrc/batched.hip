@@ -1102,23 +1102,21 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   const int npan = nbm ? (maxn + nb - 1) / nb : 0;
   // status words: [small matrices | panel pivots per big matrix | tile
   // inverses per (panel, active big matrix)]
-  DevBuf<int32_t> stat((size_t)sp.size() + nbm + (size_t)npan * std::max(1, nbm) + 1);
-  fill_value<int>((int *)stat.p, stat.n, 0, s);
+  // stream-ordered allocations: no device-wide synchronisation on release
+  StreamBuf<int32_t> stat((size_t)sp.size() + nbm + (size_t)npan * std::max(1, nbm) + 1, s);
+  const size_t stat_n = (size_t)sp.size() + nbm + (size_t)npan * std::max(1, nbm) + 1;
+  fill_value<int>((int *)stat.p, stat_n, 0, s);
   int32_t *info_small = stat.p;
   int32_t *info_panel = stat.p + sp.size();
   int32_t *info_tile = info_panel + nbm;
   if (!sp.empty()) inverse_batched<T>(sp, sn, info_small, st, s);
   std::vector<std::vector<int>> active(npan);
-  DevBuf<T> work, C, R, P;
-  DevBuf<int> piv;
+  size_t ws = 0;
+  for (int n : bn) ws += (size_t)n * nb;
+  StreamBuf<T> work(nbm ? ws : 0, s), C(nbm ? ws : 0, s), R(nbm ? ws : 0, s),
+      P(nbm ? (size_t)nbm * nb * nb : 0, s);
+  StreamBuf<int> piv(nbm ? (size_t)nbm * maxn : 0, s);
   if (nbm) {
-    size_t ws = 0;
-    for (int n : bn) ws += (size_t)n * nb;
-    work.alloc(ws);
-    C.alloc(ws);
-    R.alloc(ws);
-    P.alloc((size_t)nbm * nb * nb);
-    piv.alloc((size_t)nbm * maxn);
     std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm);
     std::vector<int *> ipv(nbm);
     size_t o = 0;
@@ -1271,8 +1269,8 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   }
   // collect the statuses (the scratch buffers are released at scope exit,
   // so the stream must drain first anyway)
-  std::vector<int32_t> hs(stat.n, 0);
-  SBIE_HIP(hipMemcpyAsync(hs.data(), stat.p, stat.n * 4, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> hs(stat_n, 0);
+  SBIE_HIP(hipMemcpyAsync(hs.data(), stat.p, stat_n * 4, hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipStreamSynchronize(s));
   std::vector<int32_t> out(nm, 0);
   for (size_t q = 0; q < sidx.size(); ++q) out[sidx[q]] = hs[q];

@@ -41,15 +41,52 @@ constexpr int kKernelSketch = 128;
 constexpr int kPgsSketch = 192;   // sketch width of wide recompression candidates
 
 // ---------------------------------------------------------------------------
-// Device arena: bump allocation from large chunks, freed together
+// Device chunks recycled between the temporary arenas of one factorisation:
+// hipMalloc and hipFree of hundreds of megabytes per level would stall the
+// host (hipFree synchronises the device).  All work runs on one stream, so a
+// chunk handed back can be reused by later launches without a wait.
+// ---------------------------------------------------------------------------
+struct ChunkCache {
+  std::multimap<size_t, void *> idle;
+  std::vector<void *> owned;
+  std::map<void *, size_t> size_of;
+  ChunkCache() = default;
+  ChunkCache(const ChunkCache &) = delete;
+  ChunkCache &operator=(const ChunkCache &) = delete;
+  ~ChunkCache() {
+    for (void *p : owned) (void)hipFree(p);
+  }
+  void *take(size_t bytes) {
+    auto it = idle.lower_bound(bytes);
+    if (it != idle.end()) {
+      void *p = it->second;
+      idle.erase(it);
+      return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(SBIE_OUT_OF_MEMORY, "device arena: hipMalloc of %zu bytes failed", bytes);
+    }
+    owned.push_back(p);
+    size_of[p] = bytes;
+    return p;
+  }
+  void give(void *p) { idle.insert({size_of[p], p}); }
+};
+
+// ---------------------------------------------------------------------------
+// Device arena: bump allocation from large chunks, freed together (to the
+// chunk cache when it has one)
 // ---------------------------------------------------------------------------
 struct Arena {
   std::vector<void *> chunks;
   size_t chunk_bytes;
+  ChunkCache *cache = nullptr;
   char *cur = nullptr;
   size_t left = 0;
   size_t total = 0;
-  explicit Arena(size_t cb = (size_t)256 << 20) : chunk_bytes(cb) {}
+  explicit Arena(size_t cb = (size_t)256 << 20, ChunkCache *c = nullptr) : chunk_bytes(cb), cache(c) {}
   Arena(const Arena &) = delete;
   Arena &operator=(const Arena &) = delete;
   ~Arena() { release(); }
@@ -59,7 +96,9 @@ struct Arena {
     if (b > left) {
       const size_t cb = std::max(chunk_bytes, b);
       void *p = nullptr;
-      if (hipMalloc(&p, cb) != hipSuccess) {
+      if (cache) {
+        p = cache->take(cb);
+      } else if (hipMalloc(&p, cb) != hipSuccess) {
         (void)hipGetLastError();
         fail(SBIE_OUT_OF_MEMORY, "device arena: hipMalloc of %zu bytes failed", cb);
       }
@@ -74,7 +113,10 @@ struct Arena {
     return p;
   }
   void release() {
-    for (void *c : chunks) (void)hipFree(c);
+    for (void *c : chunks) {
+      if (cache) cache->give(c);
+      else (void)hipFree(c);
+    }
     chunks.clear();
     cur = nullptr;
     left = 0;
@@ -608,6 +650,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       fail(SBIE_UNSUPPORTED, "pore %d radius %.3g exceeds the leaf box side %.3g", k, rad[k], leaf_h);
 
   Stager st((size_t)64 << 20);
+  ChunkCache chunk_cache;   // declared before every temporary arena: outlives them
   DevBuf<double> wl(1);
   wall_length(g, wl.p, s);
   double wall_len = 1.0;
@@ -642,7 +685,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   std::vector<int> m(nleaf);
   for (int b = 0; b < nleaf; ++b) m[b] = (int)tr.leaf_dofs[b].size();
   std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> S;  // near field of the level
-  auto level_arena = std::make_unique<Arena>((size_t)256 << 20);
+  auto level_arena = std::make_unique<Arena>((size_t)256 << 20, &chunk_cache);
   // leaf near field
   {
     std::vector<AsmDesc> ad;
@@ -714,7 +757,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     const int lev = tr.depth - li;
     const HLevel &L = tr.lv[lev];
     const int nb = L.size();
-    Arena phase_arena((size_t)256 << 20);
+    Arena phase_arena((size_t)256 << 20, &chunk_cache);
     // ---- kernel bases of this level (randomized range finder of the
     //      interpolated kernel between interaction-list grids)
     T *kfat = phase_arena.get<T>((size_t)2 * n2 * 40 * 7 * n2);
@@ -837,6 +880,9 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         T *pool = level_arena->get<T>(tot);
         fill_value<T>(pool, tot, T(0), s);
         size_t used = 0;
+        size_t nblk = 0;
+        for (int b = 0; b < nb; ++b) nblk += L.ilist[b].size() + L.nbrs[b].size();
+        Tc.reserve(2 * nblk);
         for (int b = 0; b < nb; ++b) {
           auto add = [&](int c) {
             Blk<T> bl;
@@ -851,16 +897,20 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
       gd.clear();
       std::vector<GemmDesc<T>> gd2;
+      // index of each interaction-list offset (dx, dy) among the 40 tables
+      int offset_index[7][7] = {};
+      {
+        int cnt = 0;
+        for (int ddx = -3; ddx <= 3; ++ddx)
+          for (int ddy = -3; ddy <= 3; ++ddy) {
+            if (std::max(std::abs(ddx), std::abs(ddy)) < 2) continue;
+            offset_index[ddx + 3][ddy + 3] = cnt++;
+          }
+      }
       for (int b = 0; b < nb; ++b)
         for (int c : L.ilist[b]) {
           const int dx = (int)(L.ix[c] - L.ix[b]), dy = (int)(L.iy[c] - L.iy[b]);
-          int o = 0, cnt = 0;
-          for (int ddx = -3; ddx <= 3; ++ddx)
-            for (int ddy = -3; ddy <= 3; ++ddy) {
-              if (std::max(std::abs(ddx), std::abs(ddy)) < 2) continue;
-              if (ddx == dx && ddy == dy) o = cnt;
-              ++cnt;
-            }
+          const int o = offset_index[dx + 3][dy + 3];
           T *tmp = phase_arena.get<T>((size_t)std::max(1, r[b]) * rv);
           gd.push_back({r[b], rv, ru, 0, 0, Gh[b], std::max(1, r[b]), m2l + (size_t)o * ru * rv, ru, tmp,
                         std::max(1, r[b]), T(1), T(0)});
@@ -906,7 +956,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       const std::vector<int> &E = colors[col];
       if (E.empty()) continue;
       phase_boxes.push_back(E);
-      Arena pa((size_t)128 << 20);
+      Arena pa((size_t)128 << 20, &chunk_cache);
       const int ne = (int)E.size();
       std::vector<std::vector<int>> act(ne);
       for (int e = 0; e < ne; ++e)
@@ -1208,7 +1258,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
     alloc_level_vectors(li + 1, mp);
     const std::vector<int64_t> &poff = lvl_off[li + 1];
-    auto next_arena = std::make_unique<Arena>((size_t)256 << 20);
+    auto next_arena = std::make_unique<Arena>((size_t)256 << 20, &chunk_cache);
     std::vector<T *> nphi(np_), npsi(np_), ngv(np_), nhv(np_);
     decltype(S) Sp;
     {
