@@ -268,12 +268,25 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
   }
 }
 
+// One-dimensional grid of tiles x chunks workgroups.  Workgroups are handed
+// to the eight XCDs round robin (workgroup b to XCD b % 8); when the chunk
+// count is a multiple of 8 (xcd != 0), XCD x takes the chunks ch = x (mod 8),
+// so each XCD's L2 only ever holds an eighth of the source records.
 template <int T, bool ACC>
 __global__ __launch_bounds__(kBlock) void dlp_pairs(
     const double *__restrict__ src, const double *__restrict__ xs,
     const double *__restrict__ ys, int64_t nn, int64_t chunk,
-    double *__restrict__ part) {
-  dlp_pairs_body<T, ACC>(src, xs, ys, nn, chunk, part, blockIdx.x, blockIdx.y);
+    double *__restrict__ part, int tiles, int xcd) {
+  int tile, ch;
+  if (xcd) {
+    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    ch = x + 8 * (k / tiles);
+    tile = k % tiles;
+  } else {
+    tile = blockIdx.x % tiles;
+    ch = blockIdx.x / tiles;
+  }
+  dlp_pairs_body<T, ACC>(src, xs, ys, nn, chunk, part, tile, ch);
 }
 
 // Stokeslet + rotlet columns: sum over pores of S(x_i - c_k) lambda_k
@@ -495,15 +508,17 @@ int64_t resident_pair_blocks(int tpt) {
 
 // Source chunks for the pair kernel.  All (tile, chunk) workgroups cost the
 // same; with few of them per resident slot the last, partly filled round of
-// workgroups is a large share of the run.  About seven rounds of the
+// workgroups is a large share of the run.  About eight rounds of the
 // device's resident workgroups keep that share small while the partial sums
 // (2 nn doubles per chunk, re-read by the epilogue) stay a few percent of
 // the pair time; chunks hold at least 128 sources.
 int choose_chunks(int64_t nn, int64_t tiles, int tpt) {
   const int64_t resident = resident_pair_blocks(tpt);
   const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((nn + 127) / 128, 1024));
-  const int64_t want = (7 * resident + tiles - 1) / tiles;
-  return (int)std::max<int64_t>(1, std::min(want, cap));
+  const int64_t want = (8 * resident + tiles - 1) / tiles;
+  int64_t c = std::max<int64_t>(1, std::min(want, cap));
+  if (c >= 16) c &= ~int64_t(7);   // a multiple of 8 for the XCD-aware order
+  return (int)c;
 }
 
 MatvecWork plan_matvec(const sbie_geom *g) {
@@ -552,7 +567,11 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_LAUNCH_CHECK();
   }
   const int64_t chunk = (nn + w.chunks - 1) / w.chunks;
-  dim3 grid(ceil_div(nn, (int64_t)kBlock * w.tpt), w.chunks);
+  const int tiles = (int)ceil_div(nn, (int64_t)kBlock * w.tpt);
+  const int xcd = (w.chunks % 8 == 0) ? 1 : 0;
+  const unsigned grid = (unsigned)((int64_t)tiles * w.chunks);
+  const int tiles1 = (int)ceil_div(nn, kBlock);
+  const unsigned grid1 = (unsigned)((int64_t)tiles1 * w.chunks);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // only the plain pair kernel is timed (the compensated one is a
   // different kernel, launched for true residuals)
@@ -562,14 +581,13 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_HIP(hipEventRecord(ev0, s));
   }
   if (acc) {
-    dlp_pairs<1, true><<<dim3(ceil_div(nn, kBlock), w.chunks), kBlock, 0, s>>>(
-        w.src, g->x, g->y, nn, chunk, w.part);
+    dlp_pairs<1, true><<<grid1, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles1, xcd);
   } else {
     switch (w.tpt) {
-      case 1: dlp_pairs<1, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-      case 2: dlp_pairs<2, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-      case 4: dlp_pairs<4, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
-      case 8: dlp_pairs<8, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part); break;
+      case 1: dlp_pairs<1, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
+      case 2: dlp_pairs<2, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
+      case 4: dlp_pairs<4, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
+      case 8: dlp_pairs<8, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
       default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
     }
   }

@@ -72,7 +72,7 @@ def test_matvec_dlp_only_matches_oracle(lib, tiny):
     assert np.all(y[2 * nn:] == 0.0)
 
 
-@pytest.mark.parametrize("tpt,chunks", [(1, 0), (2, 3), (4, 0), (8, 1), (4, 17)])
+@pytest.mark.parametrize("tpt,chunks", [(1, 0), (2, 3), (4, 0), (8, 1), (4, 17), (4, 8), (2, 16), (1, 24)])
 def test_matvec_launch_shapes_agree(lib, tiny, tpt, chunks):
     g, a = tiny
     dg = lib.DeviceGeometry(g)
