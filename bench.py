@@ -57,13 +57,15 @@ def main():
     ap.add_argument("--seed", type=int, default=300)
     ap.add_argument("--pc", default="all", choices=["ifmm", "bd", "both", "all"],
                     help="ifmm: IFMM at --ifmm-precision; both: that and block-diagonal; "
-                         "all: IFMM in FP64 and in FP32, and block-diagonal")
+                         "all: IFMM in FP64, FP64 factor with FP32 storage, FP32, and "
+                         "block-diagonal")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--eps", type=float, default=5e-5)
     ap.add_argument("--cheb-n", type=int, default=6)
     ap.add_argument("--ifmm-precision", type=int, default=0,
-                    help="0 = FP64 factor/apply, 1 = FP32 (mixed precision)")
+                    help="for --pc ifmm|both: 0 = FP64 factor/apply, 1 = FP32, "
+                         "2 = FP64 factor stored in FP32 for the apply")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--matvec-only", type=int, default=0,
@@ -128,10 +130,11 @@ def main():
     def make_pc(kind):
         if kind == "bd":
             return lib.BlockDiagonal(dg)
-        prec = {"ifmm": args.ifmm_precision, "ifmm_fp64": 0, "ifmm_fp32": 1}[kind]
+        prec = {"ifmm": args.ifmm_precision, "ifmm_fp64": 0, "ifmm_fp32": 1, "ifmm_mixed": 2}[kind]
         return lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=prec)
 
-    kinds = {"both": ["ifmm", "bd"], "all": ["ifmm_fp64", "ifmm_fp32", "bd"]}.get(args.pc, [args.pc])
+    kinds = {"both": ["ifmm", "bd"],
+             "all": ["ifmm_fp64", "ifmm_mixed", "ifmm_fp32", "bd"]}.get(args.pc, [args.pc])
     results = {}
     for kind in kinds:
         try:
@@ -257,7 +260,9 @@ def main():
                    "ifmm_eps": args.eps if head != "bd" else None,
                    "ifmm_cheb_n": args.cheb_n if head != "bd" else None,
                    "ifmm_precision": {"ifmm_fp64": "fp64", "ifmm_fp32": "fp32",
-                                      "ifmm": "fp32" if args.ifmm_precision else "fp64"}.get(head),
+                                      "ifmm_mixed": "fp64 factor, fp32 storage",
+                                      "ifmm": ["fp64", "fp32", "fp64 factor, fp32 storage"][
+                                          args.ifmm_precision]}.get(head),
                    "matvec_arnoldi_residual_dtype": "f64"},
         "speedup_vs_block_diagonal": (hr["solves_per_s"] / results["bd"]["solves_per_s"]
                                       if "bd" in results and head != "bd" else None),

@@ -155,7 +155,10 @@ int bd_destroy(sbie_bd *bd);
  *   cheb_n       Chebyshev nodes per direction for the initial bases.
  *   leaf_target  mean number of boundary nodes per non-empty leaf.
  *   max_depth    cap on the quadtree depth (0 = automatic).
- *   precision    0 = FP64 factor and apply, 1 = FP32.
+ *   precision    0 = FP64 factor and apply; 1 = FP32 factor and apply;
+ *                2 = FP64 factor stored a second time in FP32: ifmm_solve
+ *                reads only that copy, widening each entry to FP64 (vectors
+ *                and arithmetic stay FP64), so it moves half the bytes.
  * ifmm_solve computes x ~ A^{-1} b (device FP64, length n).
  * Errors: SBIE_UNSUPPORTED if a pore is larger than a leaf box allows;
  * SBIE_BREAKDOWN on a singular pivot. */

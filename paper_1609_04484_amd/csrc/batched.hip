@@ -141,9 +141,9 @@ __global__ __launch_bounds__(256) void gemm_tiles(const GemmDesc<T> *__restrict_
 constexpr int kGemvThreads = 1024;
 constexpr int kGemvWaves = kGemvThreads / 64;
 
-template <class T>
+template <class T, class TA>
 __global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__restrict__ descs,
-                                                          const GemvTerm<T> *__restrict__ terms) {
+                                                          const GemvTerm<T, TA> *__restrict__ terms) {
   const GemvDesc<T> d = descs[blockIdx.x];
   __shared__ T part[kGemvWaves][64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -152,19 +152,19 @@ __global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__r
 #pragma unroll
   for (int q = 0; q < 4; ++q) accw[q] = T(0);
   for (int t = d.t0; t < d.t0 + d.nt; ++t) {
-    const GemvTerm<T> tm = terms[t];
+    const GemvTerm<T, TA> tm = terms[t];
     if (!tm.trans) {
       T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
       if (lane < d.rows) {
-        const T *a = tm.A + lane;
+        const TA *a = tm.A + lane;
         int c = wv;
         for (; c + 3 * kGemvWaves < tm.cols; c += 4 * kGemvWaves) {
-          s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
-          s1 = fma(a[(size_t)(c + kGemvWaves) * tm.lda], tm.x[c + kGemvWaves], s1);
-          s2 = fma(a[(size_t)(c + 2 * kGemvWaves) * tm.lda], tm.x[c + 2 * kGemvWaves], s2);
-          s3 = fma(a[(size_t)(c + 3 * kGemvWaves) * tm.lda], tm.x[c + 3 * kGemvWaves], s3);
+          s0 = fma((T)a[(size_t)c * tm.lda], tm.x[c], s0);
+          s1 = fma((T)a[(size_t)(c + kGemvWaves) * tm.lda], tm.x[c + kGemvWaves], s1);
+          s2 = fma((T)a[(size_t)(c + 2 * kGemvWaves) * tm.lda], tm.x[c + 2 * kGemvWaves], s2);
+          s3 = fma((T)a[(size_t)(c + 3 * kGemvWaves) * tm.lda], tm.x[c + 3 * kGemvWaves], s3);
         }
-        for (; c < tm.cols; c += kGemvWaves) s0 = fma(a[(size_t)c * tm.lda], tm.x[c], s0);
+        for (; c < tm.cols; c += kGemvWaves) s0 = fma((T)a[(size_t)c * tm.lda], tm.x[c], s0);
       }
       acc = fma(tm.alpha, (s0 + s1) + (s2 + s3), acc);
     } else {
@@ -172,9 +172,9 @@ __global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__r
       for (int q = 0; q < 4; ++q) {
         const int r = wv + kGemvWaves * q;
         if (r >= d.rows) break;
-        const T *col = tm.A + (size_t)r * tm.lda;
+        const TA *col = tm.A + (size_t)r * tm.lda;
         T s = T(0);
-        for (int c = lane; c < tm.cols; c += 64) s = fma(col[c], tm.x[c], s);
+        for (int c = lane; c < tm.cols; c += 64) s = fma((T)col[c], tm.x[c], s);
         for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
         if (lane == 0) accw[q] = fma(tm.alpha, s, accw[q]);
       }
@@ -923,10 +923,10 @@ void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) 
   }
 }
 
-template <class T>
-void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T> *t, int nd, int, hipStream_t s) {
+template <class T, class TA>
+void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T, TA> *t, int nd, int, hipStream_t s) {
   if (nd == 0) return;
-  gemv_desc<T><<<nd, kGemvThreads, 0, s>>>(d, t);
+  gemv_desc<T, TA><<<nd, kGemvThreads, 0, s>>>(d, t);
   SBIE_LAUNCH_CHECK();
 }
 
@@ -936,7 +936,7 @@ void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<
   if (d.empty()) return;
   std::vector<void *> dev;
   st.put_many({{t.data(), t.size() * sizeof(GemvTerm<T>)}, {d.data(), d.size() * sizeof(GemvDesc<T>)}}, dev, s);
-  gemv_launch<T>((const GemvDesc<T> *)dev[1], (const GemvTerm<T> *)dev[0], (int)d.size(), 64, s);
+  gemv_launch<T, T>((const GemvDesc<T> *)dev[1], (const GemvTerm<T> *)dev[0], (int)d.size(), 64, s);
 }
 
 template <class T>
@@ -1370,7 +1370,7 @@ void convert(const A *src, B *dst, size_t n, hipStream_t s) {
   template void gemm_batched<T>(const std::vector<GemmDesc<T>> &, Stager &, hipStream_t); \
   template void gemv_batched<T>(const std::vector<GemvDesc<T>> &,                        \
                                 const std::vector<GemvTerm<T>> &, Stager &, hipStream_t); \
-  template void gemv_launch<T>(const GemvDesc<T> *, const GemvTerm<T> *, int, int,       \
+  template void gemv_launch<T, T>(const GemvDesc<T> *, const GemvTerm<T, T> *, int, int, \
                                hipStream_t);                                             \
   template void copy_batched<T>(const std::vector<CopyDesc<T>> &, Stager &, hipStream_t); \
   template void copy_launch<T>(const CopyDesc<T> *, int, int, hipStream_t);              \
@@ -1393,5 +1393,8 @@ template void fill_value<int>(int *, size_t, int, hipStream_t);
 template void convert<double, float>(const double *, float *, size_t, hipStream_t);
 template void convert<float, double>(const float *, double *, size_t, hipStream_t);
 template void convert<double, double>(const double *, double *, size_t, hipStream_t);
+template void convert<float, float>(const float *, float *, size_t, hipStream_t);
+template void gemv_launch<double, float>(const GemvDesc<double> *, const GemvTerm<double, float> *, int,
+                                         int, hipStream_t);
 
 }  // namespace sbie

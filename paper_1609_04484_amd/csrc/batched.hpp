@@ -20,10 +20,12 @@ struct GemmDesc {
   T alpha, beta;
 };
 
-// One term of a multi-term GEMV: alpha op(A) x with op(A) rows x cols.
-template <class T>
+// One term of a multi-term GEMV: alpha op(A) x with op(A) rows x cols.  The
+// matrix may be stored in a narrower type TA than the vectors and the
+// arithmetic (T): entries are widened as they are read.
+template <class T, class TA = T>
 struct GemvTerm {
-  const T *A;
+  const TA *A;
   const T *x;
   int lda, cols, trans;
   T alpha;
@@ -77,8 +79,8 @@ template <class T>
 void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<T>> &t,
                   Stager &st, hipStream_t s);
 // Device-resident descriptor arrays (prepared once, launched many times).
-template <class T>
-void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T> *t, int nd, int max_rows,
+template <class T, class TA = T>
+void gemv_launch(const GemvDesc<T> *d, const GemvTerm<T, TA> *t, int nd, int max_rows,
                  hipStream_t s);
 template <class T>
 void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s);

@@ -81,6 +81,7 @@ struct ChunkCache {
 // ---------------------------------------------------------------------------
 struct Arena {
   std::vector<void *> chunks;
+  std::vector<size_t> sizes;   // bytes of each chunk
   size_t chunk_bytes;
   ChunkCache *cache = nullptr;
   char *cur = nullptr;
@@ -103,6 +104,7 @@ struct Arena {
         fail(SBIE_OUT_OF_MEMORY, "device arena: hipMalloc of %zu bytes failed", cb);
       }
       chunks.push_back(p);
+      sizes.push_back(cb);
       cur = (char *)p;
       left = cb;
     }
@@ -118,6 +120,7 @@ struct Arena {
       else (void)hipFree(c);
     }
     chunks.clear();
+    sizes.clear();
     cur = nullptr;
     left = 0;
     total = 0;
@@ -468,13 +471,13 @@ auto &blk(M &map, int a, int b) {
 //   forward:  t_i = A_xx g_i;  (z-rhs of the parent) = A_zx g_i;
 //             rhs_j -= N_ji g_i with N_ji = S_ji A_xx   (j active neighbour)
 //   backward: x_i = t_i - sum_k M_ik x_k + A_xy y_i with M_ik = A_xx S_ik
-template <class T>
+template <class T, class TA = T>
 struct SolvePhase {
   GemvDesc<T> *f = nullptr;
-  GemvTerm<T> *ft = nullptr;
+  GemvTerm<T, TA> *ft = nullptr;
   int nf = 0;
   GemvDesc<T> *b = nullptr;
-  GemvTerm<T> *bt = nullptr;
+  GemvTerm<T, TA> *bt = nullptr;
   int nb = 0;
 };
 
@@ -530,62 +533,150 @@ struct IfmmImplBase {
 
 namespace {
 
+// The application's launch sequence: forward sweeps level by level, colour
+// by colour, the root, then the backward sweeps in reverse order.
+template <class T, class TA = T>
+struct SolvePlan {
+  std::vector<std::vector<SolvePhase<T, TA>>> phases;   // per eliminated level
+  GemvDesc<T> *root_d = nullptr;
+  GemvTerm<T, TA> *root_t = nullptr;
+  int root_nd = 0;
+  T *rhs0 = nullptr, *x0 = nullptr;                  // leaf-level rhs and solution
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  SolvePlan() = default;
+  SolvePlan(const SolvePlan &) = delete;
+  SolvePlan &operator=(const SolvePlan &) = delete;
+  ~SolvePlan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+  void run(hipStream_t s) const {
+    const int nl = (int)phases.size();
+    for (int l = 0; l < nl; ++l)
+      for (const auto &ph : phases[l]) gemv_launch<T, TA>(ph.f, ph.ft, ph.nf, 64, s);
+    gemv_launch<T, TA>(root_d, root_t, root_nd, 64, s);
+    for (int l = nl - 1; l >= 0; --l)
+      for (auto it = phases[l].rbegin(); it != phases[l].rend(); ++it)
+        gemv_launch<T, TA>(it->b, it->bt, it->nb, 64, s);
+  }
+  // Capture the fixed launch sequence of one application (everything between
+  // the gather of b and the scatter of x) into a HIP graph.
+  void capture() {
+    if (std::getenv("SBIE_NO_GRAPH")) return;
+    SBIE_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    SBIE_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    run(cap_stream);
+    SBIE_HIP(hipStreamEndCapture(cap_stream, &graph));
+    SBIE_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+  }
+  void apply(const int64_t *dofs, int64_t nd, const double *b, double *x, hipStream_t s) const {
+    gather_rhs<T><<<ceil_div(nd, 256), 256, 0, s>>>(dofs, nd, b, rhs0);
+    SBIE_LAUNCH_CHECK();
+    if (graph_exec)
+      SBIE_HIP(hipGraphLaunch(graph_exec, s));
+    else
+      run(s);
+    scatter_sol<T><<<ceil_div(nd, 256), 256, 0, s>>>(dofs, nd, x0, x);
+    SBIE_LAUNCH_CHECK();
+  }
+};
+
+// Host copies of one phase's descriptors (kept when an FP32 copy of the
+// application is built from an FP64 factorisation).
+template <class T>
+struct HostPhase {
+  std::vector<GemvDesc<T>> fd, bd;
+  std::vector<GemvTerm<T>> ft, bt;
+};
+
 template <class T>
 struct IfmmImpl : IfmmImplBase {
   Arena persist{(size_t)512 << 20};
   DevBuf<int64_t> leaf_dofs_all;
   int64_t n_leaf_dofs = 0;
-  std::vector<std::vector<SolvePhase<T>>> phases;   // per eliminated level
+  SolvePlan<T> plan;
+  std::vector<std::vector<SolvePhase<T>>> &phases = plan.phases;
   std::vector<T *> rhs, gsave, tbuf, vbuf, xbuf;     // per level index (0 = leaf)
   T *root_inv = nullptr;
   int root_dim = 0;
-  GemvDesc<T> *root_d = nullptr;
-  GemvTerm<T> *root_t = nullptr;
-  int root_nd = 0;
+  // FP32 storage of an FP64 factorisation (precision 2): the matrices the
+  // application reads are mirrored in FP32 at the same offsets and widened
+  // to FP64 as they are read; vectors and arithmetic stay FP64.
+  bool apply32 = false;
+  std::vector<std::vector<HostPhase<T>>> host_phases;
+  HostPhase<T> host_root;
+  Arena mirror{(size_t)256 << 20};
+  Arena mirror_desc{(size_t)16 << 20};
+  std::vector<float *> mirror_base;
+  SolvePlan<T, float> plan32;
 
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-
-  ~IfmmImpl() override {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  }
-
-  // Capture the fixed launch sequence of one application (everything between
-  // the gather of b and the scatter of x) into a HIP graph.
   void build_graph() {
-    if (std::getenv("SBIE_NO_GRAPH")) return;
-    SBIE_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-    SBIE_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-    run_sweeps(cap_stream);
-    SBIE_HIP(hipStreamEndCapture(cap_stream, &graph));
-    SBIE_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+    if (apply32) plan32.capture();
+    else plan.capture();
   }
 
   void capture_graph() override { build_graph(); }
 
   void apply(const double *b, double *x, hipStream_t s) const override {
-    const int64_t nd = n_leaf_dofs;
-    gather_rhs<T><<<ceil_div(nd, 256), 256, 0, s>>>(leaf_dofs_all.p, nd, b, rhs[0]);
-    SBIE_LAUNCH_CHECK();
-    if (graph_exec)
-      SBIE_HIP(hipGraphLaunch(graph_exec, s));
-    else
-      run_sweeps(s);
-    scatter_sol<T><<<ceil_div(nd, 256), 256, 0, s>>>(leaf_dofs_all.p, nd, xbuf[0], x);
-    SBIE_LAUNCH_CHECK();
+    if (apply32) plan32.apply(leaf_dofs_all.p, n_leaf_dofs, b, x, s);
+    else plan.apply(leaf_dofs_all.p, n_leaf_dofs, b, x, s);
   }
 
-  void run_sweeps(hipStream_t s) const {
-    const int nl = (int)phases.size();
-    for (int l = 0; l < nl; ++l)
-      for (const auto &ph : phases[l]) gemv_launch<T>(ph.f, ph.ft, ph.nf, 64, s);
-    gemv_launch<T>(root_d, root_t, root_nd, 64, s);
-    for (int l = nl - 1; l >= 0; --l)
-      for (auto it = phases[l].rbegin(); it != phases[l].rend(); ++it)
-        gemv_launch<T>(it->b, it->bt, it->nb, 64, s);
+  // the FP32 address of an FP64 array held in the persistent arena
+  float *to32(const T *p) const {
+    const char *c = reinterpret_cast<const char *>(p);
+    for (size_t i = 0; i < persist.chunks.size(); ++i) {
+      const char *base = reinterpret_cast<const char *>(persist.chunks[i]);
+      if (c >= base && c < base + persist.sizes[i])
+        return reinterpret_cast<float *>(reinterpret_cast<char *>(mirror_base[i]) + (c - base) / 2);
+    }
+    fail(SBIE_INVALID_ARGUMENT, "array outside the factorisation's storage");
+  }
+
+  // Mirror the persistent arena in FP32 and translate the solve plan.
+  void build_plan32(hipStream_t s) {
+    for (size_t i = 0; i < persist.chunks.size(); ++i) {
+      const size_t nel = persist.sizes[i] / sizeof(T);
+      float *f = mirror.get<float>(nel);
+      convert<T, float>(reinterpret_cast<const T *>(persist.chunks[i]), f, nel, s);
+      mirror_base.push_back(f);
+    }
+    auto desc32 = [&](const std::vector<GemvDesc<T>> &d) { return d; };
+    auto term32 = [&](const std::vector<GemvTerm<T>> &t) {
+      std::vector<GemvTerm<T, float>> o;
+      for (const auto &q : t) o.push_back({to32(q.A), q.x, q.lda, q.cols, q.trans, q.alpha});
+      return o;
+    };
+    auto up = [&](const auto &v) {
+      using D = typename std::decay_t<decltype(v)>::value_type;
+      if (v.empty()) return (D *)nullptr;
+      D *p = mirror_desc.get<D>(v.size());
+      SBIE_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(D), hipMemcpyHostToDevice));
+      return p;
+    };
+    plan32.phases.resize(host_phases.size());
+    for (size_t l = 0; l < host_phases.size(); ++l)
+      for (const auto &hp : host_phases[l]) {
+        SolvePhase<T, float> ph;
+        ph.f = up(desc32(hp.fd));
+        ph.ft = up(term32(hp.ft));
+        ph.nf = (int)hp.fd.size();
+        ph.b = up(desc32(hp.bd));
+        ph.bt = up(term32(hp.bt));
+        ph.nb = (int)hp.bd.size();
+        plan32.phases[l].push_back(ph);
+      }
+    plan32.root_d = up(desc32(host_root.fd));
+    plan32.root_t = up(term32(host_root.ft));
+    plan32.root_nd = (int)host_root.fd.size();
+    plan32.rhs0 = rhs[0];
+    plan32.x0 = xbuf[0];
+    host_phases.clear();
+    host_root = HostPhase<T>{};
+    SBIE_HIP(hipStreamSynchronize(s));
   }
 
   template <class D>
@@ -751,6 +842,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   };
   alloc_level_vectors(0, m);
   phases.resize(nelim);
+  if (apply32) host_phases.resize(nelim);
   int max_rank = 0;
 
   for (int li = 0; li < nelim; ++li) {
@@ -1349,6 +1441,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         ph.f = upload(fd); ph.ft = upload(ft); ph.nf = (int)fd.size();
         ph.b = upload(bd); ph.bt = upload(bt); ph.nb = (int)bd.size();
         plist.push_back(ph);
+        if (apply32) host_phases[li].push_back({fd, bd, ft, bt});
       }
     }
     SBIE_HIP(hipStreamSynchronize(s));
@@ -1390,14 +1483,18 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       std::vector<GemvDesc<T>> rdsc;
       std::vector<GemvTerm<T>> rt;
       add_gemv(rdsc, rt, xbuf[nelim], root_dim, T(0), {GemvTerm<T>{root_inv, rhs[nelim], rd, root_dim, 0, T(1)}});
-      root_d = upload(rdsc);
-      root_t = upload(rt);
-      root_nd = (int)rdsc.size();
+      plan.root_d = upload(rdsc);
+      plan.root_t = upload(rt);
+      plan.root_nd = (int)rdsc.size();
+      if (apply32) host_root = {rdsc, {}, rt, {}};
     }
   }
   SBIE_HIP(hipStreamSynchronize(s));
   clk.tick("root");
   level_arena.reset();
+  plan.rhs0 = rhs[0];
+  plan.x0 = xbuf[0];
+  if (apply32) build_plan32(s);
   if (!defer_graph) build_graph();
   clk.tick("graph");
   stats.levels = tr.depth + 1;
@@ -1427,9 +1524,10 @@ ifmm_handle *ifmm_factor_internal(const sbie_geom *g, const ifmm_params *p, hipS
   validate_geom(g);
   if (!p) fail(SBIE_INVALID_ARGUMENT, "null pointer");
   auto h = std::make_unique<ifmm_handle>();
-  if (p->precision == 0) {
+  if (p->precision == 0 || p->precision == 2) {
     auto impl = std::make_unique<IfmmImpl<double>>();
     impl->defer_graph = defer_graph;
+    impl->apply32 = p->precision == 2;
     impl->factor(g, p, s);
     h->impl = std::move(impl);
   } else if (p->precision == 1) {
@@ -1438,7 +1536,7 @@ ifmm_handle *ifmm_factor_internal(const sbie_geom *g, const ifmm_params *p, hipS
     impl->factor(g, p, s);
     h->impl = std::move(impl);
   } else {
-    fail(SBIE_INVALID_ARGUMENT, "precision must be 0 (FP64) or 1 (FP32)");
+    fail(SBIE_INVALID_ARGUMENT, "precision must be 0 (FP64), 1 (FP32) or 2 (FP64 factor, FP32 apply)");
   }
   return h.release();
 }

@@ -73,7 +73,23 @@ def test_ifmm_fp32(lib, tiny):
     assert rel(x, sig) < 5e-2
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+def test_ifmm_fp32_apply_of_fp64_factor(lib, tiny):
+    """Precision 2 stores the FP64 factorisation a second time in FP32 and
+    the application reads that copy (FP64 vectors and arithmetic): it agrees
+    with the FP64 application to FP32 rounding of the stored entries."""
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    p64 = lib.IFMM(dg, eps=1e-6, cheb_n=10, precision=0)
+    p32 = lib.IFMM(dg, eps=1e-6, cheb_n=10, precision=2)
+    for k in range(2):
+        v = dg.vector(random_vector(g.n_unknowns, 70 + k))
+        x64 = p64.solve(v).cpu().numpy()
+        x32 = p32.solve(v).cpu().numpy()
+        assert rel(x32, x64) < 1e-5
+    assert rel(p32.solve(dg.vector(f)).cpu().numpy(), sig) < 1e-4
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_gmres_with_ifmm_matches_lu(lib, tiny, precision):
     """Mixed precision: an FP32 IFMM inside FP64 FGMRES still reaches the
     FP64 solution, because the preconditioned directions are kept in FP64."""

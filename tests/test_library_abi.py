@@ -34,6 +34,20 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_has_no_undefined_symbols_of_its_own():
+    """Every symbol the library references is defined in it or in a library
+    it links (checked with immediate binding, as the loader on a GPU host
+    would find it)."""
+    code = ("import ctypes, os; ctypes.CDLL(%r, mode=os.RTLD_NOW | os.RTLD_GLOBAL); print('ok')" % LIB)
+    r = subprocess.run(["python3", "-c", code], capture_output=True, text=True)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stderr
+    out = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True,
+                         text=True, check=True).stdout
+    own = [ln.split()[-1] for ln in out.splitlines() if "sbie" in ln]
+    assert not own, own
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_binding_loads_and_matches_header():
     import paper_1609_04484_amd as p
     lib = p.load()
