@@ -778,6 +778,27 @@ __global__ __launch_bounds__(kPanelThreads) void panel_pivot_reg_kernel(const Pa
   }
 }
 
+// Final statuses of a blocked batched inversion (see inverse_batched_blocked).
+__global__ void merge_status(const int32_t *__restrict__ stat, int nsmall, int nbm, int npan, int nb,
+                             const int *__restrict__ sidx, const int *__restrict__ bidx,
+                             const int *__restrict__ tpos, int32_t *__restrict__ info) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nsmall) {
+    info[sidx[t]] = stat[t];
+    return;
+  }
+  const int b = t - nsmall;
+  if (b >= nbm) return;
+  int32_t v = stat[nsmall + b];
+  for (int it = 0; it < npan && v == 0; ++it) {
+    const int q = tpos[(size_t)it * nbm + b];
+    if (q < 0) continue;
+    const int32_t w = stat[nsmall + nbm + (size_t)it * nbm + q];
+    if (w != 0) v = it * nb + w;
+  }
+  info[bidx[b]] = v;
+}
+
 // Undo the row interchanges as column interchanges of the inverse.
 template <class T>
 __global__ __launch_bounds__(256) void unswap_columns_kernel(T *const *__restrict__ ptrs,
@@ -1267,22 +1288,24 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     unswap_columns_kernel<T><<<nbm, 256, 0, s>>>(pd_, nd_, id_);
     SBIE_LAUNCH_CHECK();
   }
-  // collect the statuses (the scratch buffers are released at scope exit,
-  // so the stream must drain first anyway)
-  std::vector<int32_t> hs(stat_n, 0);
-  SBIE_HIP(hipMemcpyAsync(hs.data(), stat.p, stat_n * 4, hipMemcpyDeviceToHost, s));
-  SBIE_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> out(nm, 0);
-  for (size_t q = 0; q < sidx.size(); ++q) out[sidx[q]] = hs[q];
-  for (int b = 0; b < nbm; ++b)
-    if (hs[sp.size() + b] != 0) out[bidx[b]] = hs[sp.size() + b];
-  for (int it = 0; it < npan; ++it)
-    for (size_t q = 0; q < active[it].size(); ++q) {
-      const int32_t v = hs[sp.size() + nbm + (size_t)it * nbm + q];
-      if (v != 0 && out[bidx[active[it][q]]] == 0) out[bidx[active[it][q]]] = it * nb + v;
-    }
-  SBIE_HIP(hipMemcpyAsync(info_dev, out.data(), nm * 4, hipMemcpyHostToDevice, s));
-  SBIE_HIP(hipStreamSynchronize(s));
+  // Merge the statuses on the device (no host round trip): a small matrix
+  // reports its own status; a big one its panel-pivot failure, else the
+  // first failing pivot-block inverse (as a column index).  tpos[it * nbm +
+  // b] is matrix b's slot among the active matrices of panel it, or -1.
+  {
+    std::vector<int> tpos((size_t)std::max(1, npan) * std::max(1, nbm), -1);
+    for (int it = 0; it < npan; ++it)
+      for (size_t q = 0; q < active[it].size(); ++q) tpos[(size_t)it * nbm + active[it][q]] = (int)q;
+    std::vector<void *> dev;
+    st.put_many({{sidx.data(), sidx.size() * sizeof(int)}, {bidx.data(), bidx.size() * sizeof(int)},
+                 {tpos.data(), tpos.size() * sizeof(int)}},
+                dev, s);
+    const int work_items = (int)sidx.size() + nbm;
+    merge_status<<<ceil_div(std::max(1, work_items), 256), 256, 0, s>>>(
+        stat.p, (int)sidx.size(), nbm, npan, nb, (const int *)dev[0], (const int *)dev[1],
+        (const int *)dev[2], info_dev);
+    SBIE_LAUNCH_CHECK();
+  }
 }
 
 template <class T>

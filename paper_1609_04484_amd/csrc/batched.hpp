@@ -95,7 +95,8 @@ void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
 
 // Same, with matrices larger than a threshold inverted by blocked
 // Gauss-Jordan with partial pivoting whose rank-nb updates are batched GEMMs
-// (spread over all compute units); synchronises the stream.
+// (spread over all compute units).  Stream-ordered: info_dev is written by
+// the last launch, so read it after a synchronisation.
 template <class T>
 void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                              int32_t *info_dev, Stager &st, hipStream_t s);
