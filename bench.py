@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--chunks", type=int, default=0,
                     help="pair-kernel source chunks (0 = the library's occupancy-based choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stored-gemv", default="",
+                    help="also time y = A x with A assembled and stored densely (HBM-bound "
+                         "comparison) on this workload, e.g. pipe200")
     ap.add_argument("--cpu-rows", type=int, default=512)
     args = ap.parse_args()
 
@@ -136,6 +139,7 @@ def main():
     kinds = {"both": ["ifmm", "bd"],
              "all": ["ifmm_fp64", "ifmm_mixed", "ifmm_fp32", "bd"]}.get(args.pc, [args.pc])
     results = {}
+    sigmas = {}
     for kind in kinds:
         try:
             pc = make_pc(kind)
@@ -153,7 +157,7 @@ def main():
         torch.cuda.synchronize()
         lib.kernel_timing(True)
         lib.kernel_time()
-        iters, relres, relpc, tmv, tpc, tar, tfac = [], [], [], [], [], [], []
+        iters, relres, relpc, tmv, tpc, tar, tfac, tstep = [], [], [], [], [], [], [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
             tf0 = time.perf_counter()
@@ -161,6 +165,8 @@ def main():
             torch.cuda.synchronize()
             tfac.append(time.perf_counter() - tf0)
             r = lib.gmres(dg, fd, pc=pc, tol=args.tol, max_iter=args.max_iter)
+            torch.cuda.synchronize()
+            tstep.append(time.perf_counter() - tf0)
             stats = pc.stats() if kind != "bd" else None
             pc.close()
             iters.append(r.iters)
@@ -174,8 +180,12 @@ def main():
         lib.kernel_timing(False)
         kms, kcount = lib.kernel_time()
         sigma = r.sigma
+        sigmas[kind] = sigma
         results[kind] = dict(
             solves_per_s=args.steps / elapsed, ms_per_solve=1e3 * elapsed / args.steps,
+            s_per_solve_median=float(np.median(tstep)), s_per_solve_min=float(np.min(tstep)),
+            s_per_solve_max=float(np.max(tstep)),
+            iterate_only_solves_per_s=1.0 / float(np.mean(np.array(tstep) - np.array(tfac))),
             iters=iters, rel_res_true=max(relres), rel_res_pc=max(relpc),
             converged=all(x <= args.tol for x in relres),
             t_matvec_s=float(np.mean(tmv)), t_precond_apply_s=float(np.mean(tpc)),
@@ -198,6 +208,13 @@ def main():
     if not results:
         print("no preconditioner could be built", file=sys.stderr)
         sys.exit(1)
+    # no dense oracle exists at this size: each IFMM solution is compared with
+    # the block-diagonal one (an independent FP64 solve to the same tolerance)
+    if "bd" in sigmas:
+        ref = sigmas["bd"]
+        for k in results:
+            results[k]["solution_rel_diff_vs_block_diagonal"] = float(
+                torch.linalg.vector_norm(sigmas[k] - ref) / torch.linalg.vector_norm(ref))
     ifmm_kinds = [k for k in results if k != "bd"]
     head = max(ifmm_kinds, key=lambda k: results[k]["solves_per_s"]) if ifmm_kinds else "bd"
     hr = results[head]
@@ -241,6 +258,41 @@ def main():
                           f"this is an upper bound on CPU solves/s")}
         log(f"[bench] cpu baseline: {cpu}")
 
+    stored = None
+    if args.stored_gemv:
+        # the matrix-free product against a stored dense matrix (assembled by
+        # the library's own kernel) streamed by a plain library GEMV
+        gs = make_geometry(args.stored_gemv, {"pipe200": 100, "tiny": 1}.get(args.stored_gemv, 1))
+        dgs = lib.DeviceGeometry(gs)
+        ns = gs.n_unknowns
+        rows = np.arange(ns, dtype=np.int64)
+        amat = lib.assemble(dgs, rows, rows)
+        xs = dgs.vector(np.random.default_rng(5).standard_normal(ns))
+        ref = lib.matvec(dgs, xs)
+        y = torch.mv(amat, xs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            y = torch.mv(amat, xs)
+        e1.record()
+        torch.cuda.synchronize()
+        t_gemv = e0.elapsed_time(e1) / 10 * 1e-3
+        lib.matvec(dgs, xs, out=ref)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            lib.matvec(dgs, xs, out=ref)
+        e1.record()
+        torch.cuda.synchronize()
+        t_free = e0.elapsed_time(e1) / 10 * 1e-3
+        stored = {"workload": args.stored_gemv, "n": ns, "matrix_GB": ns * ns * 8 / 1e9,
+                  "stored_gemv_ms": 1e3 * t_gemv, "stored_gemv_GBps": ns * ns * 8 / t_gemv / 1e9,
+                  "matrix_free_ms": 1e3 * t_free,
+                  "max_rel_diff": float((y - ref).abs().max() / ref.abs().max())}
+        del amat
+        log(f"[bench] stored-matrix comparison: {stored}")
+
     line = {
         "metric": METRIC,
         "value": hr["solves_per_s"],
@@ -271,6 +323,7 @@ def main():
         "solves": results,
         "matvec_effective_GBps": matvec_gbs,
         "oracle_sampled_row_residual": row_res,
+        "stored_matrix_comparison": stored,
     }
     print(json.dumps(line), flush=True)
 
