@@ -130,6 +130,101 @@ __global__ __launch_bounds__(256) void gemm_tiles(const GemmDesc<T> *__restrict_
   }
 }
 
+// FP64 GEMM tile on the matrix cores: the same 64 x 64 tiles and LDS staging
+// as gemm_tiles, with each of the four waves computing a 32 x 32 quarter as
+// 2 x 2 blocks of v_mfma_f64_16x16x4.  Operand layout of that instruction
+// (checked on the device): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16], and register v of lane l receives D[l / 16 + 4 v][l % 16].
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *__restrict__ descs,
+                                                       const int2 *__restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const GemmDesc<double> d = descs[tl.x];
+  const int tiles_m = (d.m + 63) >> 6;
+  const int row0 = (tl.y % tiles_m) * 64;
+  const int col0 = (tl.y / tiles_m) * 64;
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  mfma_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  // the next stage's global values are loaded into registers while the
+  // current stage is multiplied out of LDS
+  double ra[4], rb[4];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int r, kk;
+      if (!d.ta) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
+      const int gi = row0 + r, gk = k0 + kk;
+      ra[q] = (gi < d.m && gk < d.k) ? (d.ta ? d.A[gk + (size_t)gi * d.lda] : d.A[gi + (size_t)gk * d.lda]) : 0.0;
+      int c;
+      if (!d.tb) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
+      const int gj = col0 + c, gk2 = k0 + kk;
+      rb[q] = (gj < d.n && gk2 < d.k) ? (d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb]) : 0.0;
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if (!d.ta) As[e >> 6][e & 63] = ra[q]; else As[e & 15][e >> 4] = ra[q];
+      if (!d.tb) Bs[e & 15][e >> 4] = rb[q]; else Bs[e >> 6][e & 63] = rb[q];
+    }
+  };
+  if (d.k > 0) load_stage(0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    store_stage();
+    __syncthreads();
+    if (k0 + 16 < d.k) load_stage(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[ks + lk][wr + 16 * q + li];
+        b[q] = Bs[ks + lk][wc + 16 * q + li];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + wr + 16 * x + lk + 4 * v;
+        const int c = col0 + wc + 16 * y + li;
+        if (r >= d.m || c >= d.n) continue;
+        double *p = d.C + r + (size_t)c * d.ldc;
+        double val = d.alpha * acc[x][y][v];
+        if (d.beta != 0.0) val = fma(d.beta, *p, val);
+        *p = val;
+      }
+}
+
+// FP64 products go to the matrix cores, FP32 ones to the vector tile.
+template <class T>
+void launch_gemm_tiles(unsigned nt, const GemmDesc<T> *dd, const int2 *td, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value)
+    gemm_tiles_mfma<<<nt, 256, 0, s>>>(dd, td);
+  else
+    gemm_tiles<T><<<nt, 256, 0, s>>>(dd, td);
+  SBIE_LAUNCH_CHECK();
+}
+
 // ----------------------------------------------------------------------------
 // GEMV: one workgroup per descriptor (at most 64 rows)
 // ----------------------------------------------------------------------------
@@ -933,8 +1028,7 @@ void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) 
     std::vector<void *> dev;
     st.put_many({{keep.data(), keep.size() * sizeof(GemmDesc<T>)}, {tiles.data() + t0, nt * sizeof(int2)}},
                 dev, s);
-    gemm_tiles<T><<<(unsigned)nt, 256, 0, s>>>((const GemmDesc<T> *)dev[0], (const int2 *)dev[1]);
-    SBIE_LAUNCH_CHECK();
+    launch_gemm_tiles<T>((unsigned)nt, (const GemmDesc<T> *)dev[0], (const int2 *)dev[1], s);
   }
   for (const auto &sp : splits) {
     const int64_t e = (int64_t)sp.g.m * sp.g.n;
@@ -1247,8 +1341,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     };
     auto gemm_step = [&](const GemmPrep &g) {
       if (g.nt == 0) return;
-      gemm_tiles<T><<<g.nt, 256, 0, s>>>((const GemmDesc<T> *)(db + g.d), (const int2 *)(db + g.t));
-      SBIE_LAUNCH_CHECK();
+      launch_gemm_tiles<T>(g.nt, (const GemmDesc<T> *)(db + g.d), (const int2 *)(db + g.t), s);
     };
     for (size_t it = 0; it < steps.size(); ++it) {
       const Step &q = steps[it];
