@@ -873,6 +873,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_pivot_reg_kernel(const Pa
   }
 }
 
+template <class T>
+__global__ void set_diagonal(T *A, int n, T v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) A[i + (size_t)i * n] = v;
+}
+
 // Final statuses of a blocked batched inversion (see inverse_batched_blocked).
 __global__ void merge_status(const int32_t *__restrict__ stat, int nsmall, int nbm, int npan, int nb,
                              const int *__restrict__ sidx, const int *__restrict__ bidx,
@@ -1087,17 +1092,23 @@ void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s) 
 // column interchanges are undone through LDS on the way out.
 template <class T, int NMAX>
 __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs, const int *__restrict__ ns,
-                                                     int32_t *__restrict__ info) {
+                                                     int32_t *__restrict__ info,
+                                                     const T *const *__restrict__ srcs = nullptr,
+                                                     const int *__restrict__ lds = nullptr) {
   __shared__ T xk[NMAX], xp[NMAX], prow[NMAX];
   __shared__ T out[NMAX][NMAX + 1];
   __shared__ int ipv[NMAX], lab[NMAX];
   const int b = blockIdx.x;
   const int n = ns[b];
   T *A = ptrs[b];
+  // the matrix is read from srcs[b] (leading dimension lds[b]) when given,
+  // else from A itself; the inverse is written to A (leading dimension n)
+  const T *src = srcs ? srcs[b] : A;
+  const int ld = srcs ? lds[b] : n;
   const int i = threadIdx.x;
   T r[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? A[i + (size_t)c * n] : T(0);
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : T(0);
   bool failed = false;
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -1231,7 +1242,11 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   StreamBuf<T> work(nbm ? ws : 0, s), C(nbm ? ws : 0, s), R(nbm ? ws : 0, s),
       P(nbm ? (size_t)nbm * nb * nb : 0, s);
   StreamBuf<int> piv(nbm ? (size_t)nbm * maxn : 0, s);
+  StreamBuf<T> negid(nbm ? (size_t)nb * nb : 0, s);   // -I of order nb
   if (nbm) {
+    fill_value<T>(negid.p, (size_t)nb * nb, T(0), s);
+    set_diagonal<T><<<1, 64, 0, s>>>(negid.p, nb, T(-1));
+    SBIE_LAUNCH_CHECK();
     std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm);
     std::vector<int *> ipv(nbm);
     size_t o = 0;
@@ -1284,9 +1299,9 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       return r;
     };
     struct Step {
-      size_t pd = 0, pp = 0, pn = 0;
+      size_t pd = 0, pp = 0, pn = 0, psrc = 0, pld = 0;
       int npd = 0, hmax = 0, pmax = 0;
-      CopyPrep cP, cC, cZ, cRz, cRow, cPin;
+      CopyPrep cC, cRow;
       GemmPrep gR, gUpd, gCol;
     };
     std::vector<Step> steps;
@@ -1294,8 +1309,9 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       const int k0 = it * nb;
       std::vector<PanelDesc<T>> pd;
       std::vector<T *> pp;
-      std::vector<int> pn;
-      std::vector<CopyDesc<T>> cP, cC, cZ, cRz, cRow, cPin;
+      std::vector<const T *> psrc;
+      std::vector<int> pn, pld;
+      std::vector<CopyDesc<T>> cC, cRow;
       std::vector<GemmDesc<T>> gR, gUpd, gCol;
       for (int b = 0; b < nbm; ++b) {
         const int n = bn[b];
@@ -1306,15 +1322,19 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         pd.push_back({A, woff[b], ipv[b], n, k0, pb, info_panel + b});
         pp.push_back(poff[b]);
         pn.push_back(pb);
-        cP.push_back({A + k0 + (size_t)k0 * n, n, poff[b], pb, pb, pb, 0, 0, T(1)});
-        cC.push_back({A + (size_t)k0 * n, n, coff[b], n, n, pb, 0, 0, T(1)});
-        cZ.push_back({nullptr, 1, coff[b] + k0, n, pb, pb, 0, 0, T(0)});
+        psrc.push_back(A + k0 + (size_t)k0 * n);
+        pld.push_back(n);
+        // C = A[:, p] with its pivot rows replaced by -I: then the update
+        // A -= C R leaves rows p to be overwritten by R, and A[:, p] = -C P
+        // puts P itself in the pivot block
+        if (k0 > 0) cC.push_back({A + (size_t)k0 * n, n, coff[b], n, k0, pb, 0, 0, T(1)});
+        cC.push_back({negid.p, nb, coff[b] + k0, n, pb, pb, 0, 0, T(1)});
+        if (k0 + pb < n)
+          cC.push_back({A + k0 + pb + (size_t)k0 * n, n, coff[b] + k0 + pb, n, n - k0 - pb, pb, 0, 0, T(1)});
         gR.push_back({pb, n, pb, 0, 0, poff[b], pb, A + k0, n, roff[b], pb, T(1), T(0)});
-        cRz.push_back({nullptr, 1, roff[b] + (size_t)k0 * pb, pb, pb, pb, 0, 0, T(0)});
         gUpd.push_back({n, n, pb, 0, 0, coff[b], n, roff[b], pb, A, n, T(-1), T(1)});
         cRow.push_back({roff[b], pb, A + k0, n, pb, n, 0, 0, T(1)});
         gCol.push_back({n, pb, pb, 0, 0, coff[b], n, poff[b], pb, A + (size_t)k0 * n, n, T(-1), T(0)});
-        cPin.push_back({poff[b], pb, A + k0 + (size_t)k0 * n, n, pb, pb, 0, 0, T(1)});
       }
       if (pd.empty()) break;
       Step st_;
@@ -1324,15 +1344,13 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       st_.pd = add(pd.data(), pd.size() * sizeof(PanelDesc<T>));
       st_.pp = add(pp.data(), pp.size() * sizeof(T *));
       st_.pn = add(pn.data(), pn.size() * sizeof(int));
-      st_.cP = prep_copy(cP);
+      st_.psrc = add(psrc.data(), psrc.size() * sizeof(T *));
+      st_.pld = add(pld.data(), pld.size() * sizeof(int));
       st_.cC = prep_copy(cC);
-      st_.cZ = prep_copy(cZ);
       st_.gR = prep_gemm(gR);
-      st_.cRz = prep_copy(cRz);
       st_.gUpd = prep_gemm(gUpd);
       st_.cRow = prep_copy(cRow);
       st_.gCol = prep_gemm(gCol);
-      st_.cPin = prep_copy(cPin);
       steps.push_back(st_);
     }
     char *db = (char *)st.put(blob.data(), blob.size(), s);
@@ -1351,25 +1369,23 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       else
         panel_pivot_kernel<T><<<(unsigned)q.npd, 256, 0, s>>>(dd);
       SBIE_LAUNCH_CHECK();
-      copy_step(q.cP);                                                  // P = A_pp
       {                                                                 // P = A_pp^-1
         T *const *pp_ = (T *const *)(db + q.pp);
         const int *pn_ = (const int *)(db + q.pn);
+        const T *const *ps_ = (const T *const *)(db + q.psrc);
+        const int *pl_ = (const int *)(db + q.pld);
         int32_t *inf = info_tile + it * nbm;
         if (q.pmax <= 32)
-          gj_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf);
+          gj_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
         else
-          gj_wave_kernel<T, 64><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf);
+          gj_wave_kernel<T, 64><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
         SBIE_LAUNCH_CHECK();
       }
-      copy_step(q.cC);                                                  // C = A[:, p]
-      copy_step(q.cZ);                                                  // C[p, :] = 0
+      copy_step(q.cC);                                                  // C = A[:, p], C[p, :] = -I
       gemm_step(q.gR);                                                  // R = P A[p, :]
-      copy_step(q.cRz);                                                 // R[:, p] = 0
       gemm_step(q.gUpd);                                                // A -= C R
       copy_step(q.cRow);                                                // A[p, :] = R
       gemm_step(q.gCol);                                                // A[:, p] = -C P
-      copy_step(q.cPin);                                                // A_pp = P
     }
     std::vector<void *> dev;
     st.put_many({{bp.data(), bp.size() * sizeof(T *)}, {bn.data(), bn.size() * sizeof(int)},
