@@ -30,7 +30,7 @@ PAIR_FLOPS = 19                # algorithmic flops per node pair of the matvec
 # read off a plain 1 GiB device copy; profiles/dlp_pairs_pipe1000_hbm_counters.md).
 # Valid only for the kernel source they were taken with: reported as null
 # once matvec.hip changes.
-PAIR_TRAFFIC = {"matvec_sha256": "03bc71a11aa8fa0cef28c73ed33c4bf20b0d75e6935f66b59f3eb8ce7b699241", "bytes_per_launch": 196028826,
+PAIR_TRAFFIC = {"matvec_sha256": "62d6dcdc01836aa85a248db2865465de7424b98a701c4a0a6720d8f7626db3f4", "bytes_per_launch": 148246835,
                 "workload": "pipe1000"}
 
 
