@@ -130,6 +130,10 @@ struct PgsDesc {
   int ldw, r0, rmax;
   double tol;
   int *count;
+  // the candidates are already orthogonal to W's columns [0, orth_from)
+  // (projected out beforehand), so accepted columns are re-orthogonalised
+  // only against the later ones; 0 = against all of them
+  int orth_from;
 };
 template <class T>
 void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s);

@@ -1281,10 +1281,13 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         if (aug[a].c == 0) {
           continue;
         }
+        // both candidate sets are orthogonal to W[j][:, :r[j]] (projected
+        // twice above; the sketch only combines projected columns)
         if (ysk[a])
-          pd.push_back({ysk[a], m[j], m[j], kPgsSketch, W[j], m[j], r[j], m[j], eps, counts.p + a});
+          pd.push_back({ysk[a], m[j], m[j], kPgsSketch, W[j], m[j], r[j], m[j], eps, counts.p + a, r[j]});
         else
-          pd.push_back({aug[a].cand, m[j], m[j], aug[a].c, W[j], m[j], r[j], m[j], eps, counts.p + a});
+          pd.push_back({aug[a].cand, m[j], m[j], aug[a].c, W[j], m[j], r[j], m[j], eps, counts.p + a,
+                        r[j]});
       }
       fill_value<int>(counts.p, aug.size() + 1, 0, s);
       pgs_batched<T>(pd, st, s);
