@@ -4,7 +4,8 @@
 One step = one whole solve of the hot path with the inputs already resident
 in HBM: preconditioner build (IFMM or block-diagonal) + flexible GMRES to a
 true relative residual of 1e-10 (every Arnoldi step, matvec and residual in
-FP64).  Prints one JSON line.
+FP64).  The timed steps cycle over a few seeded pipes of the same family and
+size.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--pc ifmm|bd|both]
 """
@@ -55,13 +56,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pipe1000")
     ap.add_argument("--seed", type=int, default=300)
+    ap.add_argument("--geometries", type=int, default=3,
+                    help="timed steps cycle over this many pipes (seeds seed, seed+1, ...): "
+                         "the IFMM's iteration count varies by +-30%% between pipes of the "
+                         "same family, so one pipe alone is not representative")
     ap.add_argument("--pc", default="all", choices=["ifmm", "bd", "both", "all"],
                     help="ifmm: IFMM at --ifmm-precision; both: that and block-diagonal; "
                          "all: IFMM in FP64, FP64 factor with FP32 storage, FP32, and "
                          "block-diagonal")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
-    ap.add_argument("--eps", type=float, default=5e-5)
+    ap.add_argument("--eps", type=float, default=1e-5)
+    ap.add_argument("--eps-fp32", type=float, default=1e-4,
+                    help="IFMM tolerance of the FP32 factorisation (--pc all): FP32 "
+                         "rounding in the elimination swamps tolerances much below this")
     ap.add_argument("--cheb-n", type=int, default=6)
     ap.add_argument("--ifmm-precision", type=int, default=0,
                     help="for --pc ifmm|both: 0 = FP64 factor/apply, 1 = FP32, "
@@ -95,12 +103,16 @@ def main():
     torch.cuda.set_device(0)
     if args.tpt or args.chunks:
         lib.set_matvec_shape(args.tpt or 4, args.chunks)
-    g = make_geometry(args.workload, args.seed)
-    f = poiseuille_rhs(g)
-    dg = lib.DeviceGeometry(g)
-    fd = dg.vector(f)
+    seeds = [args.seed + i for i in range(max(1, args.geometries))]
+    geoms = [make_geometry(args.workload, sd) for sd in seeds]
+    rhs = [poiseuille_rhs(gg) for gg in geoms]
+    dgeoms = [lib.DeviceGeometry(gg) for gg in geoms]
+    frhs = [d.vector(ff) for d, ff in zip(dgeoms, rhs)]
+    if len({gg.n_unknowns for gg in geoms}) != 1:
+        raise SystemExit("the geometries of one bench run must share their size")
+    g, f, dg, fd = geoms[0], rhs[0], dgeoms[0], frhs[0]
     nn, n = g.n_nodes, g.n_unknowns
-    log(f"[bench] workload {args.workload} seed {args.seed}: Nn={nn} n={n}")
+    log(f"[bench] workload {args.workload} seeds {seeds}: Nn={nn} n={n}")
 
     if args.matvec_only:
         x = dg.vector(np.random.default_rng(7).standard_normal(n))
@@ -130,11 +142,12 @@ def main():
               flush=True)
         return
 
-    def make_pc(kind):
+    def make_pc(kind, dg=dg):
         if kind == "bd":
             return lib.BlockDiagonal(dg)
         prec = {"ifmm": args.ifmm_precision, "ifmm_fp64": 0, "ifmm_fp32": 1, "ifmm_mixed": 2}[kind]
-        return lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=prec)
+        eps = args.eps_fp32 if kind == "ifmm_fp32" else args.eps
+        return lib.IFMM(dg, eps=eps, cheb_n=args.cheb_n, precision=prec)
 
     kinds = {"both": ["ifmm", "bd"],
              "all": ["ifmm_fp64", "ifmm_mixed", "ifmm_fp32", "bd"]}.get(args.pc, [args.pc])
@@ -160,11 +173,12 @@ def main():
         iters, relres, relpc, tmv, tpc, tar, tfac, tstep = [], [], [], [], [], [], [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
+            dgk, fdk = dgeoms[k % len(dgeoms)], frhs[k % len(dgeoms)]
             tf0 = time.perf_counter()
-            pc = make_pc(kind)
+            pc = make_pc(kind, dgk)
             torch.cuda.synchronize()
             tfac.append(time.perf_counter() - tf0)
-            r = lib.gmres(dg, fd, pc=pc, tol=args.tol, max_iter=args.max_iter)
+            r = lib.gmres(dgk, fdk, pc=pc, tol=args.tol, max_iter=args.max_iter)
             torch.cuda.synchronize()
             tstep.append(time.perf_counter() - tf0)
             stats = pc.stats() if kind != "bd" else None
@@ -219,7 +233,10 @@ def main():
     head = max(ifmm_kinds, key=lambda k: results[k]["solves_per_s"]) if ifmm_kinds else "bd"
     hr = results[head]
 
-    # sampled-row check of the last solution against the oracle's rows
+    # sampled-row check of the last solution against the oracle's rows (the
+    # last step's pipe; every kind ends on the same one)
+    last = (args.steps - 1) % len(dgeoms)
+    g, f = geoms[last], rhs[last]
     from oracle import dlp
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(n, 64, replace=False))
@@ -308,8 +325,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: pipe [0,50]x[0,1], 4096 wall nodes, "
                                f"1000 pores x 64 nodes, Poiseuille inflow",
-                   "seed": args.seed, "n_unknowns": n, "pc": head, "tol": args.tol,
-                   "ifmm_eps": args.eps if head != "bd" else None,
+                   "seeds": seeds, "n_unknowns": n, "pc": head, "tol": args.tol,
+                   "ifmm_eps": (args.eps_fp32 if head == "ifmm_fp32" else args.eps)
+                               if head != "bd" else None,
                    "ifmm_cheb_n": args.cheb_n if head != "bd" else None,
                    "ifmm_precision": {"ifmm_fp64": "fp64", "ifmm_fp32": "fp32",
                                       "ifmm_mixed": "fp64 factor, fp32 storage",

@@ -519,20 +519,27 @@ __global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ pt
 // ----------------------------------------------------------------------------
 // Truncated pivoted Gram-Schmidt (rank-revealing), one workgroup per problem
 // ----------------------------------------------------------------------------
-// One workgroup of kPgsThreads per candidate block.  The candidates are only
-// read: their residual norms (squared, in LDS) are downdated by the squared
-// projection on every accepted column, and the chosen candidate is projected
-// against the accepted columns twice (classical Gram-Schmidt, twice) when it
-// is picked, then normalised and appended.  Downdating loses about one unit
-// roundoff of the candidate's original norm, far below the truncation
-// threshold.  Columns of W below orth_from are left out of the projection:
-// the caller has projected them out of the candidates already.  Reductions go
-// through wave shuffles, then across the 16 waves in LDS.
+// One workgroup of kPgsThreads per candidate block.  In FP64 the candidates
+// are only read: their residual norms (squared, in LDS) are downdated by the
+// squared projection on every accepted column, and the chosen candidate is
+// projected against the accepted columns twice (classical Gram-Schmidt,
+// twice) when it is picked, then normalised and appended.  Downdating loses
+// about one unit roundoff of the candidate's original norm, far below the
+// truncation threshold.  Columns of W below orth_from are left out of the
+// projection: the caller has projected them out of the candidates already.
+// In FP32 every accepted column is projected out of the candidates in place
+// (see pgs_kernel).  Reductions go through wave shuffles, then across the 16
+// waves in LDS.
 constexpr int kPgsThreads = 1024;
 constexpr int kPgsWaves = kPgsThreads / 64;
 
 template <class T>
 __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__restrict__ descs) {
+  // FP64 columns: residual norms are downdated and the candidates only read.
+  // FP32 columns are orthonormal only to about 6e-8, which would spoil a
+  // downdated norm at thresholds of tol^2 ~ 1e-9: they are projected in place
+  // and re-orthogonalised against the whole basis instead.
+  constexpr bool kDowndate = sizeof(T) == sizeof(double);
   extern __shared__ unsigned char shraw[];
   const PgsDesc<T> d = descs[blockIdx.x];
   double *norms = reinterpret_cast<double *>(shraw);   // c
@@ -576,7 +583,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
     for (int i = tid; i < d.m; i += kPgsThreads) q[i] = d.R[i + (size_t)p * d.ldr];
     __syncthreads();
     const int rc = d.r0 + k;
-    const int c0 = min(d.orth_from, rc);
+    const int c0 = kDowndate ? min(d.orth_from, rc) : 0;
     for (int pass = 0; pass < 2 && c0 < rc; ++pass) {
       for (int col = c0 + wv; col < rc; col += kPgsWaves) {
         const T *w = d.W + (size_t)col * d.ldw;
@@ -618,17 +625,34 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
     if (tid == 0) norms[p] = 0.0;
     __syncthreads();
     ++k;
-    // downdate the residual norms by the projections on the new column; the
-    // candidates themselves stay as given (read, never written)
     for (int j = wv; j < d.c; j += kPgsWaves) {
       // a column already below the tolerance can never be chosen again and
       // its residual norm only decreases: leave it alone
       if (!(norms[j] > tol2)) continue;
-      const T *col = d.R + (size_t)j * d.ldr;
-      double dt = 0.0;
-      for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);
-      for (int o = 32; o > 0; o >>= 1) dt += __shfl_down(dt, o, 64);
-      if (lane == 0) norms[j] = fma(-dt, dt, norms[j]);
+      if constexpr (kDowndate) {
+        // downdate the residual norm by the projection on the new column;
+        // the candidate itself stays as given (read, never written)
+        const T *col = d.R + (size_t)j * d.ldr;
+        double dt = 0.0;
+        for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);
+        for (int o = 32; o > 0; o >>= 1) dt += __shfl_down(dt, o, 64);
+        if (lane == 0) norms[j] = fma(-dt, dt, norms[j]);
+      } else {
+        // project the new column out of the candidate and recompute its norm
+        T *col = d.R + (size_t)j * d.ldr;
+        double dt = 0.0;
+        for (int i = lane; i < d.m; i += 64) dt = fma((double)q[i], (double)col[i], dt);
+        for (int o = 32; o > 0; o >>= 1) dt += __shfl_down(dt, o, 64);
+        dt = __shfl(dt, 0, 64);
+        double sq2 = 0.0;
+        for (int i = lane; i < d.m; i += 64) {
+          const T v = (T)((double)col[i] - dt * (double)q[i]);
+          col[i] = v;
+          sq2 = fma((double)v, (double)v, sq2);
+        }
+        for (int o = 32; o > 0; o >>= 1) sq2 += __shfl_down(sq2, o, 64);
+        if (lane == 0) norms[j] = sq2;
+      }
     }
     __syncthreads();
   }
