@@ -308,17 +308,20 @@ __global__ __launch_bounds__(256) void copy_desc(const CopyDesc<T> *__restrict__
   const CopyDesc<T> d = descs[blockIdx.x];
   const int c0 = blockIdx.y * 16;
   if (c0 >= d.cols) return;
-  const int c1 = c0 + 16 < d.cols ? c0 + 16 : d.cols;
-  for (int c = c0; c < c1; ++c)
-    for (int r = threadIdx.x; r < d.rows; r += blockDim.x) {
-      T *p = d.dst + r + (size_t)c * d.ldd;
-      if (!d.acc && d.alpha == T(0)) {   // zero fill: the source is not read
-        *p = T(0);
-        continue;
-      }
-      const T v = d.trans ? d.src[c + (size_t)r * d.lds] : d.src[r + (size_t)c * d.lds];
-      *p = d.acc ? fma(d.alpha, v, *p) : d.alpha * v;
+  // the block's (row, column) pairs are spread over all threads, so short
+  // columns (a few rows) still keep the workgroup busy
+  const int nc = d.cols - c0 < 16 ? d.cols - c0 : 16;
+  const int tot = d.rows * nc;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int c = c0 + e / d.rows, r = e % d.rows;
+    T *p = d.dst + r + (size_t)c * d.ldd;
+    if (!d.acc && d.alpha == T(0)) {   // zero fill: the source is not read
+      *p = T(0);
+      continue;
     }
+    const T v = d.trans ? d.src[c + (size_t)r * d.lds] : d.src[r + (size_t)c * d.lds];
+    *p = d.acc ? fma(d.alpha, v, *p) : d.alpha * v;
+  }
 }
 
 template <class T>
@@ -661,17 +664,23 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
 
 
 // ----------------------------------------------------------------------------
-// Blocked Gauss-Jordan with partial pivoting, helper kernels.  For the panel
-// of columns [k0, k0 + pb) of every matrix: pivot rows are chosen by an LU
-// with partial pivoting of a copy of the tall panel (rows k0..n) -- the same
-// rows Gauss-Jordan with partial pivoting would choose -- and the row swaps
-// are applied to the whole matrix.
+// Blocked Gauss-Jordan with partial pivoting by columns, helper kernels.
+// The matrices are column-major, so pivoting by columns makes every
+// interchange a copy of contiguous columns; this is Gauss-Jordan with
+// partial (row) pivoting applied to the transpose, and the inverse of the
+// transpose is the transpose of the inverse.  For the panel of rows
+// [k0, k0 + pb) of every matrix: pivot columns are chosen by an elimination
+// with partial pivoting of a copy of the wide panel (columns k0..n) -- the
+// same columns Gauss-Jordan would choose -- and the interchanges are applied
+// to whole columns.  lab[j] follows which original column sits at position
+// j; the rows of the finished inverse are put back in that order at the end.
 // ----------------------------------------------------------------------------
 template <class T>
 struct PanelDesc {
   T *A;          // n x n, ld n
   T *work;       // (n - k0) x pb scratch
-  int *ipiv;     // n entries (global row chosen at step k)
+  int *ipiv;     // n entries (column chosen at step k; fallback kernel only)
+  int *lab;      // n entries: original column now at each position
   int n, k0, pb;
   int32_t *info;
 };
@@ -684,8 +693,9 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const PanelDesc<T> *__
   const int tid = threadIdx.x;
   const int h = d.n - d.k0;
   T *W = d.work;
-  for (int c = 0; c < d.pb; ++c)
-    for (int r = tid; r < h; r += 256) W[r + (size_t)c * h] = d.A[(d.k0 + r) + (size_t)(d.k0 + c) * d.n];
+  // W (h x pb): W[r + c h] = A[k0 + c, k0 + r], the panel transposed
+  for (int r = tid; r < h; r += 256)
+    for (int c = 0; c < d.pb; ++c) W[r + (size_t)c * h] = d.A[(d.k0 + c) + (size_t)(d.k0 + r) * d.n];
   __syncthreads();
   for (int t = 0; t < d.pb; ++t) {
     double best = -1.0;
@@ -732,29 +742,38 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const PanelDesc<T> *__
     }
     __syncthreads();
   }
-  // apply the swaps to whole rows of A, in order
+  // apply the interchanges to whole columns of A, in order
   for (int t = 0; t < d.pb; ++t) {
     const int k = d.k0 + t, p = d.ipiv[k];
-    if (p != k)
-      for (int c = tid; c < d.n; c += 256) {
-        const T a = d.A[k + (size_t)c * d.n];
-        d.A[k + (size_t)c * d.n] = d.A[p + (size_t)c * d.n];
-        d.A[p + (size_t)c * d.n] = a;
+    if (p != k) {
+      for (int r = tid; r < d.n; r += 256) {
+        const T a = d.A[r + (size_t)k * d.n];
+        d.A[r + (size_t)k * d.n] = d.A[r + (size_t)p * d.n];
+        d.A[r + (size_t)p * d.n] = a;
       }
+      if (tid == 0) {
+        const int x = d.lab[k];
+        d.lab[k] = d.lab[p];
+        d.lab[p] = x;
+      }
+    }
     __syncthreads();
   }
 }
 
-// Same result for panels of at most kPanelRegRows rows, with two barriers
-// per column instead of a dozen: each of 256 threads keeps up to three rows
-// of the panel in registers (row i belongs to thread i % 256, slot i / 256).
-// A step takes a wave-shuffle argmax, one barrier to combine the four waves,
-// then the owners of rows t and p post both rows in LDS and, after the
-// second barrier, every thread reads the pivot row from there and updates
-// its rows.  LDS buffers alternate between steps, so the next step's posts
-// cannot overwrite what a slower wave still reads.  Finally the swaps are
-// applied to A as one permutation of the touched rows, one column per thread,
-// all loads of a column in flight together.
+// Same result for panels of at most kPanelRegRows columns, with two barriers
+// per step instead of a dozen: each of 256 threads keeps up to three
+// columns of the panel in registers (column j belongs to thread j % 256,
+// slot j / 256; a column's pb entries are contiguous in memory).  Below,
+// "row" names such a register vector: the elimination is the one of the
+// transposed panel.  A step takes a wave-shuffle argmax, one barrier to
+// combine the four waves, then the owner of the pivot vector posts it in LDS
+// and, after the second barrier, every thread updates its unused vectors.
+// Vectors never move between threads; the choice order alone defines the
+// interchanges.  LDS buffers alternate between steps, so the next step's
+// posts cannot overwrite what a slower wave still reads.  Finally the
+// interchanges are applied to A as one permutation of the touched columns,
+// staged through LDS in blocks of 64 rows.
 template <int I, int N, class F>
 __device__ __forceinline__ void static_for(F &&f) {
   if constexpr (I < N) {
@@ -763,91 +782,103 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
+// Four waves with three vectors per lane (panels of up to 768 columns).  A
+// single wave with six vectors per lane (no workgroup barriers) measured
+// slower: the steps are bound by their own latency chain, not the barriers.
 constexpr int kPanelThreads = 256;
 constexpr int kPanelSlots = 3;
 constexpr int kPanelRegRows = kPanelThreads * kPanelSlots;
 
-template <class T>
-__global__ __launch_bounds__(kPanelThreads) void panel_pivot_reg_kernel(const PanelDesc<T> *__restrict__ descs) {
+// workgroup barrier; for a single wave, LDS completion and a wave barrier
+template <int THREADS>
+__device__ __forceinline__ void panel_sync() {
+  if constexpr (THREADS == 64) {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+template <class T, int THREADS, int SLOTS>
+__global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDesc<T> *__restrict__ descs) {
   constexpr int PB = 32;
-  constexpr int NW = kPanelThreads / 64;
+  constexpr int NW = THREADS / 64;
   const PanelDesc<T> d = descs[blockIdx.x];
   __shared__ double w_v[2][NW];
   __shared__ int w_i[2][NW];
-  __shared__ T prow[2][PB], xrow[2][PB];
+  __shared__ T prow[2][PB];
+  __shared__ int chosen[PB];
   __shared__ int u_pos[2 * PB], u_src[2 * PB];
   __shared__ int s_nu;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int h = d.n - d.k0, pb = d.pb;
-  T row[kPanelSlots][PB];
+  T row[SLOTS][PB];
 #pragma unroll
-  for (int q = 0; q < kPanelSlots; ++q) {
-    const int r = tid + kPanelThreads * q;
+  for (int q = 0; q < SLOTS; ++q) {
+    const int r = tid + THREADS * q;
 #pragma unroll
     for (int c = 0; c < PB; ++c)
-      row[q][c] = (r < h && c < pb) ? d.A[(d.k0 + r) + (size_t)(d.k0 + c) * d.n] : T(0);
+      row[q][c] = (r < h && c < pb) ? d.A[(d.k0 + c) + (size_t)(d.k0 + r) * d.n] : T(0);
   }
   // one step per column, expanded at compile time (static_for) so that every
-  // column index is a constant and the rows stay in registers
+  // column index is a constant and the rows stay in registers.  Rows never
+  // trade places during the elimination: a chosen row is marked as used
+  // (bit q of `used`) and posted to LDS, and only unused rows are updated.
   bool failed = false;
+  unsigned used = 0;
   static_for<0, PB>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
     if (failed || t >= pb) return;
     const int par = t & 1;
-    // argmax of |row[t]| over rows r >= t (lowest row on ties)
+    // argmax of |row[t]| over the unused rows (lowest row on ties)
     double v = -1.0;
-    int bi = t;
+    int bi = 0x7fffffff;
 #pragma unroll
-    for (int q = 0; q < kPanelSlots; ++q) {
-      const int r = tid + kPanelThreads * q;
+    for (int q = 0; q < SLOTS; ++q) {
+      const int r = tid + THREADS * q;
       const double a = fabs((double)row[q][t]);
-      if (r >= t && r < h && a > v) { v = a; bi = r; }
+      if (r < h && !((used >> q) & 1u) && a > v) { v = a; bi = r; }
     }
+    // butterfly: every lane ends with the wave's argmax
     for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_down(v, o, 64);
-      const int oi = __shfl_down(bi, o, 64);
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
       if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
     }
-    if (lane == 0) { w_v[par][wv] = v; w_i[par][wv] = bi; }
-    __syncthreads();
-    double pv = w_v[par][0];
-    int p = w_i[par][0];
+    double pv = v;
+    int p = bi;
+    if constexpr (NW > 1) {
+      if (lane == 0) { w_v[par][wv] = v; w_i[par][wv] = bi; }
+      __syncthreads();
+      pv = w_v[par][0];
+      p = w_i[par][0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w)
-      if (w_v[par][w] > pv || (w_v[par][w] == pv && w_i[par][w] < p)) { pv = w_v[par][w]; p = w_i[par][w]; }
+      for (int w = 1; w < NW; ++w)
+        if (w_v[par][w] > pv || (w_v[par][w] == pv && w_i[par][w] < p)) { pv = w_v[par][w]; p = w_i[par][w]; }
+    }
     if (!(pv > 0.0) || !isfinite(pv)) {
       if (tid == 0) *d.info = d.k0 + t + 1;
       failed = true;
       return;
     }
-    if (tid == 0) d.ipiv[d.k0 + t] = d.k0 + p;
-    // owners post rows p (the pivot) and t
+    if (tid == 0) chosen[t] = p;
+    // the owner posts the pivot row
 #pragma unroll
-    for (int q = 0; q < kPanelSlots; ++q) {
-      const int r = tid + kPanelThreads * q;
-      if (r == p) {
+    for (int q = 0; q < SLOTS; ++q) {
+      if (tid + THREADS * q == p) {
 #pragma unroll
-        for (int c = 0; c < PB; ++c) prow[par][c] = row[q][c];
-      }
-      if (r == t) {
-#pragma unroll
-        for (int c = 0; c < PB; ++c) xrow[par][c] = row[q][c];
+        for (int c = t; c < PB; ++c) prow[par][c] = row[q][c];
+        used |= 1u << q;
       }
     }
-    __syncthreads();
-    // rows t and p trade places; every row below t is updated
+    panel_sync<THREADS>();
+    const T pinv = T(1) / prow[par][t];
 #pragma unroll
-    for (int q = 0; q < kPanelSlots; ++q) {
-      const int r = tid + kPanelThreads * q;
-      if (r == t) {
-#pragma unroll
-        for (int c = 0; c < PB; ++c) row[q][c] = prow[par][c];
-      } else if (r == p) {
-#pragma unroll
-        for (int c = 0; c < PB; ++c) row[q][c] = xrow[par][c];
-      }
-      if (r > t && r < h) {
-        const T l = row[q][t] / prow[par][t];
+    for (int q = 0; q < SLOTS; ++q) {
+      const int r = tid + THREADS * q;
+      if (r < h && !((used >> q) & 1u)) {
+        const T l = row[q][t] * pinv;
         row[q][t] = l;
 #pragma unroll
         for (int c = t + 1; c < PB; ++c) row[q][c] = fma(-l, prow[par][c], row[q][c]);
@@ -855,45 +886,58 @@ __global__ __launch_bounds__(kPanelThreads) void panel_pivot_reg_kernel(const Pa
     }
   });
   if (failed) return;
-  // the combined permutation of the touched rows, from replaying the swaps
-  // on row labels
-  __syncthreads();
+  // the panel's permutation of columns: position k0 + t receives the t-th
+  // chosen column; the columns of [k0, k0 + pb) that were not chosen move,
+  // in increasing order, to the positions that chosen columns from beyond
+  // the panel left (in the order they were chosen)
+  panel_sync<THREADS>();
   if (tid == 0) {
     int nu = 0;
-    auto slot = [&](int r) {
-      for (int i = 0; i < nu; ++i)
-        if (u_pos[i] == r) return i;
-      u_pos[nu] = r;
-      u_src[nu] = r;
-      return nu++;
-    };
-    for (int t = 0; t < pb; ++t) {
-      const int k = d.k0 + t, p = d.ipiv[k];
-      if (p == k) continue;
-      const int a = slot(k), b = slot(p);
-      const int x = u_src[a];
-      u_src[a] = u_src[b];
-      u_src[b] = x;
-    }
+    unsigned top = 0;
+    for (int t = 0; t < pb; ++t)
+      if (chosen[t] < pb) top |= 1u << chosen[t];
+    for (int t = 0; t < pb; ++t)
+      if (chosen[t] != t) {
+        u_pos[nu] = d.k0 + t;
+        u_src[nu] = d.k0 + chosen[t];
+        ++nu;
+      }
+    int x = 0;
+    for (int t = 0; t < pb; ++t)
+      if (chosen[t] >= pb) {
+        while ((top >> x) & 1u) ++x;
+        u_pos[nu] = d.k0 + chosen[t];
+        u_src[nu] = d.k0 + x;
+        ++nu;
+        ++x;
+      }
     s_nu = nu;
   }
-  __syncthreads();
+  panel_sync<THREADS>();
   const int nu = s_nu;
   if (nu == 0) return;
-  // blocks of 64 columns staged through LDS: all touched values of the block
-  // are loaded before any is stored
+  {
+    // the column labels follow the same permutation (all reads before the
+    // barrier, all writes after it)
+    const int v = tid < nu ? d.lab[u_src[tid]] : 0;
+    panel_sync<THREADS>();
+    if (tid < nu) d.lab[u_pos[tid]] = v;
+  }
+  // blocks of 64 rows staged through LDS: all touched values of the block
+  // are loaded before any is stored; each column segment is one coalesced
+  // 512-byte access
   __shared__ T stage[2 * PB][64];
-  for (int c0 = 0; c0 < d.n; c0 += 64) {
-    for (int e = tid; e < nu * 64; e += kPanelThreads) {
-      const int i = e >> 6, c = c0 + (e & 63);
-      if (c < d.n) stage[i][e & 63] = d.A[u_src[i] + (size_t)c * d.n];
+  for (int r0 = 0; r0 < d.n; r0 += 64) {
+    for (int e = tid; e < nu * 64; e += THREADS) {
+      const int i = e >> 6, r = r0 + (e & 63);
+      if (r < d.n) stage[i][e & 63] = d.A[r + (size_t)u_src[i] * d.n];
     }
-    __syncthreads();
-    for (int e = tid; e < nu * 64; e += kPanelThreads) {
-      const int i = e >> 6, c = c0 + (e & 63);
-      if (c < d.n) d.A[u_pos[i] + (size_t)c * d.n] = stage[i][e & 63];
+    panel_sync<THREADS>();
+    for (int e = tid; e < nu * 64; e += THREADS) {
+      const int i = e >> 6, r = r0 + (e & 63);
+      if (r < d.n) d.A[r + (size_t)u_pos[i] * d.n] = stage[i][e & 63];
     }
-    __syncthreads();
+    panel_sync<THREADS>();
   }
 }
 
@@ -923,22 +967,35 @@ __global__ void merge_status(const int32_t *__restrict__ stat, int nsmall, int n
   info[bidx[b]] = v;
 }
 
-// Undo the row interchanges as column interchanges of the inverse.
+// Column labels start as the identity.
+__global__ void iota_labels(int *const *__restrict__ labs, const int *__restrict__ ns) {
+  int *lab = labs[blockIdx.y];
+  const int n = ns[blockIdx.y];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n) lab[j] = j;
+}
+
+// Undo the column interchanges as a row permutation of the inverse: row k
+// of the eliminated matrix is row lab[k] of the inverse.  One workgroup per
+// (matrix, block of kUnpermCols columns); each column goes through LDS.
+constexpr int kUnpermCols = 16;
 template <class T>
-__global__ __launch_bounds__(256) void unswap_columns_kernel(T *const *__restrict__ ptrs,
+__global__ __launch_bounds__(256) void unpermute_rows_kernel(T *const *__restrict__ ptrs,
                                                              const int *__restrict__ ns,
-                                                             int *const *__restrict__ ipivs) {
-  T *A = ptrs[blockIdx.x];
-  const int n = ns[blockIdx.x];
-  const int *ipiv = ipivs[blockIdx.x];
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = ipiv[k];
-    if (p != k)
-      for (int r = threadIdx.x; r < n; r += 256) {
-        const T a = A[r + (size_t)k * n];
-        A[r + (size_t)k * n] = A[r + (size_t)p * n];
-        A[r + (size_t)p * n] = a;
-      }
+                                                             int *const *__restrict__ labs) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = reinterpret_cast<T *>(shraw);
+  const int n = ns[blockIdx.y];
+  const int c0 = blockIdx.x * kUnpermCols;
+  if (c0 >= n) return;
+  T *A = ptrs[blockIdx.y];
+  const int *lab = labs[blockIdx.y];
+  const int c1 = min(n, c0 + kUnpermCols);
+  for (int c = c0; c < c1; ++c) {
+    T *col = A + (size_t)c * n;
+    for (int k = threadIdx.x; k < n; k += 256) buf[k] = col[k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += 256) col[lab[k]] = buf[k];
     __syncthreads();
   }
 }
@@ -1212,6 +1269,70 @@ __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs
     for (int c = 0; c < n; ++c) A[i + (size_t)c * n] = out[i][lab[c]];
 }
 
+// Gauss-Jordan inverse without interchanges, one wave per matrix of order
+// n <= NMAX, read from srcs[b] (leading dimension lds[b]) and written to
+// ptrs[b] (leading dimension n).  For the pivot blocks of the blocked
+// inverse: their columns were chosen by partial pivoting over the whole
+// panel, so the diagonal already holds the pivots an interchanging
+// elimination of the transposed block would take (the pivots of an
+// elimination without interchanges are ratios of leading principal minors,
+// the same for a matrix and its transpose).  Lane i keeps row i in
+// registers; the scaled pivot row is broadcast through LDS.
+template <class T, int NMAX>
+__global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict__ ptrs,
+                                                           const int *__restrict__ ns,
+                                                           int32_t *__restrict__ info,
+                                                           const T *const *__restrict__ srcs,
+                                                           const int *__restrict__ lds) {
+  __shared__ T prow[2][NMAX];
+  const int b = blockIdx.x;
+  const int n = ns[b];
+  T *A = ptrs[b];
+  const T *src = srcs[b];
+  const int ld = lds[b];
+  const int i = threadIdx.x;
+  T r[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : T(0);
+  bool failed = false;
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (failed || k >= n) return;
+    constexpr int par = k & 1;
+    if (i == k) {
+      const T inv = T(1) / r[k];
+      r[k] = T(1);
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) {
+        r[c] *= inv;
+        prow[par][c] = r[c];
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the row is in LDS
+    __builtin_amdgcn_wave_barrier();
+    // prow[k] holds 1 / pivot: a zero pivot fails here.  (No early return
+    // inside the expanded loop: with one, the compiler keeps every step's
+    // values live and spills them; the next step's test skips the rest.)
+    if (!isfinite((double)prow[par][k])) {
+      if (i == 0) info[b] = k + 1;
+      failed = true;
+    }
+    if (i != k && i < n) {
+      const T f = r[k];
+      r[k] = T(0);
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[par][c], r[c]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  });
+  if (failed) return;
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < n) A[i + (size_t)c * n] = r[c];
+  }
+}
+
 template <class T>
 void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                      int32_t *info_dev, Stager &st, hipStream_t s) {
@@ -1250,6 +1371,8 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   int maxn = 0;
   for (int n : bn) maxn = std::max(maxn, n);
   const int npan = nbm ? (maxn + nb - 1) / nb : 0;
+  if ((size_t)maxn * sizeof(T) > 64 * 1024)
+    fail(SBIE_UNSUPPORTED, "matrix of order %d too large for the blocked inverse", maxn);
   // status words: [small matrices | panel pivots per big matrix | tile
   // inverses per (panel, active big matrix)]
   // stream-ordered allocations: no device-wide synchronisation on release
@@ -1265,14 +1388,14 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   for (int n : bn) ws += (size_t)n * nb;
   StreamBuf<T> work(nbm ? ws : 0, s), C(nbm ? ws : 0, s), R(nbm ? ws : 0, s),
       P(nbm ? (size_t)nbm * nb * nb : 0, s);
-  StreamBuf<int> piv(nbm ? (size_t)nbm * maxn : 0, s);
+  StreamBuf<int> piv(nbm ? (size_t)nbm * maxn : 0, s), labb(nbm ? (size_t)nbm * maxn : 0, s);
   StreamBuf<T> negid(nbm ? (size_t)nb * nb : 0, s);   // -I of order nb
   if (nbm) {
     fill_value<T>(negid.p, (size_t)nb * nb, T(0), s);
     set_diagonal<T><<<1, 64, 0, s>>>(negid.p, nb, T(-1));
     SBIE_LAUNCH_CHECK();
     std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm);
-    std::vector<int *> ipv(nbm);
+    std::vector<int *> ipv(nbm), lbv(nbm);
     size_t o = 0;
     for (int b = 0; b < nbm; ++b) {
       woff[b] = work.p + o;
@@ -1281,7 +1404,17 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       o += (size_t)bn[b] * nb;
       poff[b] = P.p + (size_t)b * nb * nb;
       ipv[b] = piv.p + (size_t)b * maxn;
+      lbv[b] = labb.p + (size_t)b * maxn;
     }
+    std::vector<void *> mdev;
+    st.put_many({{bp.data(), bp.size() * sizeof(T *)}, {bn.data(), bn.size() * sizeof(int)},
+                 {lbv.data(), lbv.size() * sizeof(int *)}},
+                mdev, s);
+    auto *mat_dev = (T *const *)mdev[0];
+    auto *n_dev = (const int *)mdev[1];
+    auto *lab_dev = (int *const *)mdev[2];
+    iota_labels<<<dim3(ceil_div(maxn, 256), nbm), 256, 0, s>>>(lab_dev, n_dev);
+    SBIE_LAUNCH_CHECK();
     // Every panel step's descriptors are known up front: they are packed
     // into one host blob and uploaded in a single transfer, and the steps
     // then launch back to back with no host work in between.
@@ -1343,22 +1476,24 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         active[it].push_back(b);
         const int pb = std::min(nb, n - k0);
         T *A = bp[b];
-        pd.push_back({A, woff[b], ipv[b], n, k0, pb, info_panel + b});
+        pd.push_back({A, woff[b], ipv[b], lbv[b], n, k0, pb, info_panel + b});
         pp.push_back(poff[b]);
         pn.push_back(pb);
         psrc.push_back(A + k0 + (size_t)k0 * n);
         pld.push_back(n);
-        // C = A[:, p] with its pivot rows replaced by -I: then the update
-        // A -= C R leaves rows p to be overwritten by R, and A[:, p] = -C P
-        // puts P itself in the pivot block
-        if (k0 > 0) cC.push_back({A + (size_t)k0 * n, n, coff[b], n, k0, pb, 0, 0, T(1)});
-        cC.push_back({negid.p, nb, coff[b] + k0, n, pb, pb, 0, 0, T(1)});
+        // p = [k0, k0 + pb).  C = A[p, :] (pb x n) with its pivot columns
+        // replaced by -I: then the update A -= R C leaves columns p to be
+        // overwritten by R = A[:, p] P, and A[p, :] = -P C puts P itself in
+        // the pivot block
+        if (k0 > 0) cC.push_back({A + k0, n, coff[b], pb, pb, k0, 0, 0, T(1)});
+        cC.push_back({negid.p, nb, coff[b] + (size_t)k0 * pb, pb, pb, pb, 0, 0, T(1)});
         if (k0 + pb < n)
-          cC.push_back({A + k0 + pb + (size_t)k0 * n, n, coff[b] + k0 + pb, n, n - k0 - pb, pb, 0, 0, T(1)});
-        gR.push_back({pb, n, pb, 0, 0, poff[b], pb, A + k0, n, roff[b], pb, T(1), T(0)});
-        gUpd.push_back({n, n, pb, 0, 0, coff[b], n, roff[b], pb, A, n, T(-1), T(1)});
-        cRow.push_back({roff[b], pb, A + k0, n, pb, n, 0, 0, T(1)});
-        gCol.push_back({n, pb, pb, 0, 0, coff[b], n, poff[b], pb, A + (size_t)k0 * n, n, T(-1), T(0)});
+          cC.push_back({A + k0 + (size_t)(k0 + pb) * n, n, coff[b] + (size_t)(k0 + pb) * pb, pb, pb,
+                        n - k0 - pb, 0, 0, T(1)});
+        gR.push_back({n, pb, pb, 0, 0, A + (size_t)k0 * n, n, poff[b], pb, roff[b], n, T(1), T(0)});
+        gUpd.push_back({n, n, pb, 0, 0, roff[b], n, coff[b], pb, A, n, T(-1), T(1)});
+        cRow.push_back({roff[b], n, A + (size_t)k0 * n, n, n, pb, 0, 0, T(1)});
+        gCol.push_back({pb, n, pb, 0, 0, poff[b], pb, coff[b], pb, A + k0, n, T(-1), T(0)});
       }
       if (pd.empty()) break;
       Step st_;
@@ -1388,8 +1523,9 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     for (size_t it = 0; it < steps.size(); ++it) {
       const Step &q = steps[it];
       const auto *dd = (const PanelDesc<T> *)(db + q.pd);
-      if (q.hmax <= kPanelRegRows && kPanel <= 32)
-        panel_pivot_reg_kernel<T><<<(unsigned)q.npd, kPanelThreads, 0, s>>>(dd);   // choose rows, swap
+      static_assert(kPanel <= 32, "the register panels hold 32 entries per vector");
+      if (q.hmax <= kPanelRegRows)                                      // choose columns, swap
+        panel_pivot_reg_kernel<T, kPanelThreads, kPanelSlots><<<(unsigned)q.npd, kPanelThreads, 0, s>>>(dd);
       else
         panel_pivot_kernel<T><<<(unsigned)q.npd, 256, 0, s>>>(dd);
       SBIE_LAUNCH_CHECK();
@@ -1399,26 +1535,18 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         const T *const *ps_ = (const T *const *)(db + q.psrc);
         const int *pl_ = (const int *)(db + q.pld);
         int32_t *inf = info_tile + it * nbm;
-        if (q.pmax <= 32)
-          gj_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
-        else
-          gj_wave_kernel<T, 64><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
+        static_assert(kPanel <= 32, "pivot blocks are inverted by 32-row waves");
+        gj_nopiv_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
         SBIE_LAUNCH_CHECK();
       }
-      copy_step(q.cC);                                                  // C = A[:, p], C[p, :] = -I
-      gemm_step(q.gR);                                                  // R = P A[p, :]
-      gemm_step(q.gUpd);                                                // A -= C R
-      copy_step(q.cRow);                                                // A[p, :] = R
-      gemm_step(q.gCol);                                                // A[:, p] = -C P
+      copy_step(q.cC);                                                  // C = A[p, :], C[:, p] = -I
+      gemm_step(q.gR);                                                  // R = A[:, p] P
+      gemm_step(q.gUpd);                                                // A -= R C
+      copy_step(q.cRow);                                                // A[:, p] = R
+      gemm_step(q.gCol);                                                // A[p, :] = -P C
     }
-    std::vector<void *> dev;
-    st.put_many({{bp.data(), bp.size() * sizeof(T *)}, {bn.data(), bn.size() * sizeof(int)},
-                 {ipv.data(), ipv.size() * sizeof(int *)}},
-                dev, s);
-    auto *pd_ = (T *const *)dev[0];
-    auto *nd_ = (const int *)dev[1];
-    auto *id_ = (int *const *)dev[2];
-    unswap_columns_kernel<T><<<nbm, 256, 0, s>>>(pd_, nd_, id_);
+    unpermute_rows_kernel<T><<<dim3(ceil_div(maxn, kUnpermCols), nbm), 256, (size_t)maxn * sizeof(T), s>>>(
+        mat_dev, n_dev, lab_dev);
     SBIE_LAUNCH_CHECK();
   }
   // Merge the statuses on the device (no host round trip): a small matrix

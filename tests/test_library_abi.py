@@ -48,6 +48,23 @@ def test_library_has_no_undefined_symbols_of_its_own():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_every_kernel_launched_from_host_code_has_device_code():
+    """Each host-side launch stub names a kernel whose gfx950 code object
+    entry (``<name>.kd``) is in the library.  A source edited between the
+    device and the host compilation passes breaks this, and such a launch
+    aborts the process on the GPU."""
+    syms = subprocess.run(["nm", LIB], capture_output=True, text=True, check=True).stdout
+    stubs = {ln.split()[-1].split("__device_stub__", 1)[1]
+             for ln in syms.splitlines() if "__device_stub__" in ln}
+    assert stubs
+    strings = subprocess.run(["strings", "-n", "8", LIB], capture_output=True, text=True,
+                             check=True).stdout
+    kd = [w for w in strings.split() if w.endswith(".kd")]
+    missing = sorted(st for st in stubs if not any(st + ".kd" in w for w in kd))
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_binding_loads_and_matches_header():
     import paper_1609_04484_amd as p
     lib = p.load()
