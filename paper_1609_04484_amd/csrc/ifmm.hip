@@ -1335,8 +1335,9 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         recs.push_back(rc);
         gone[E[e]] = 1;
       }
-      SBIE_HIP(hipStreamSynchronize(s));
-      st.reset();
+      // no wait here: the next phase's host work overlaps these launches
+      // (the staging ring waits by itself when it wraps, and the phase
+      // arena's chunks are only reused by later launches on this stream)
       (void)rold;
       clk.tick("elim_couplings");
     }
