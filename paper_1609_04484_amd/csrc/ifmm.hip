@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <cmath>
 #include <map>
@@ -650,27 +651,29 @@ struct IfmmImpl : IfmmImplBase {
       for (const auto &q : t) o.push_back({to32(q.A), q.x, q.lda, q.cols, q.trans, q.alpha});
       return o;
     };
-    auto up = [&](const auto &v) {
-      using D = typename std::decay_t<decltype(v)>::value_type;
-      if (v.empty()) return (D *)nullptr;
-      D *p = mirror_desc.get<D>(v.size());
-      SBIE_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(D), hipMemcpyHostToDevice));
-      return p;
-    };
+    Packed pk;
+    struct Offs { size_t f, ft, b, bt; int nf, nb; };
+    std::vector<std::vector<Offs>> offs(host_phases.size());
+    for (size_t l = 0; l < host_phases.size(); ++l)
+      for (const auto &hp : host_phases[l])
+        offs[l].push_back({pk.add(desc32(hp.fd)), pk.add(term32(hp.ft)), pk.add(desc32(hp.bd)),
+                           pk.add(term32(hp.bt)), (int)hp.fd.size(), (int)hp.bd.size()});
+    const size_t root_d = pk.add(desc32(host_root.fd)), root_t = pk.add(term32(host_root.ft));
+    char *base = send(pk, mirror_desc, s);
     plan32.phases.resize(host_phases.size());
     for (size_t l = 0; l < host_phases.size(); ++l)
-      for (const auto &hp : host_phases[l]) {
+      for (const Offs &o : offs[l]) {
         SolvePhase<T, float> ph;
-        ph.f = up(desc32(hp.fd));
-        ph.ft = up(term32(hp.ft));
-        ph.nf = (int)hp.fd.size();
-        ph.b = up(desc32(hp.bd));
-        ph.bt = up(term32(hp.bt));
-        ph.nb = (int)hp.bd.size();
+        ph.f = at<GemvDesc<T>>(base, o.f);
+        ph.ft = at<GemvTerm<T, float>>(base, o.ft);
+        ph.nf = o.nf;
+        ph.b = at<GemvDesc<T>>(base, o.b);
+        ph.bt = at<GemvTerm<T, float>>(base, o.bt);
+        ph.nb = o.nb;
         plan32.phases[l].push_back(ph);
       }
-    plan32.root_d = up(desc32(host_root.fd));
-    plan32.root_t = up(term32(host_root.ft));
+    plan32.root_d = at<GemvDesc<T>>(base, root_d);
+    plan32.root_t = at<GemvTerm<T, float>>(base, root_t);
     plan32.root_nd = (int)host_root.fd.size();
     plan32.rhs0 = rhs[0];
     plan32.x0 = xbuf[0];
@@ -685,6 +688,34 @@ struct IfmmImpl : IfmmImplBase {
     D *p = persist.get<D>(v.size());
     SBIE_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(D), hipMemcpyHostToDevice));
     return p;
+  }
+
+  // Descriptor arrays of many solve phases packed into one host block and
+  // sent with one stream-ordered copy (instead of one blocking copy each).
+  // The host blocks stay alive until the factorisation's final wait.
+  struct Packed {
+    std::vector<char> bytes;
+    template <class D>
+    size_t add(const std::vector<D> &v) {
+      if (v.empty()) return SIZE_MAX;
+      const size_t o = (bytes.size() + 255) & ~size_t(255);
+      bytes.resize(o + v.size() * sizeof(D));
+      std::memcpy(bytes.data() + o, v.data(), v.size() * sizeof(D));
+      return o;
+    }
+  };
+  std::vector<std::vector<char>> sent_blocks;
+  char *send(Packed &pk, Arena &a, hipStream_t s) {
+    if (pk.bytes.empty()) return nullptr;
+    char *p = a.get<char>(pk.bytes.size());
+    sent_blocks.push_back(std::move(pk.bytes));
+    const std::vector<char> &b = sent_blocks.back();
+    SBIE_HIP(hipMemcpyAsync(p, b.data(), b.size(), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  template <class D>
+  static D *at(char *base, size_t o) {
+    return o == SIZE_MAX ? nullptr : reinterpret_cast<D *>(base + o);
   }
 
   // split a y-block of `rows` rows into <= 64-row GEMV descriptors
@@ -1417,8 +1448,10 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       std::unordered_map<int, const Rec *> byi;
       for (const Rec &rc : recs) byi[rc.i] = &rc;
       std::vector<SolvePhase<T>> &plist = phases[li];
+      Packed pk;
+      struct Offs { size_t f, ft, b, bt; int nf, nb; };
+      std::vector<Offs> offs;
       for (const auto &E : phase_boxes) {
-        SolvePhase<T> ph;
         std::vector<GemvDesc<T>> fd, bd;
         std::vector<GemvTerm<T>> ft, bt;
         for (int i : E) {
@@ -1442,10 +1475,19 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
           if (ri > 0) terms.push_back({rc.axy, px_ + poff[pp] + in_par[i], mi, ri, 0, T(1)});
           add_gemv(bd, bt, lx + off[i], mi, T(1), terms, lt + off[i]);
         }
-        ph.f = upload(fd); ph.ft = upload(ft); ph.nf = (int)fd.size();
-        ph.b = upload(bd); ph.bt = upload(bt); ph.nb = (int)bd.size();
-        plist.push_back(ph);
+        offs.push_back({pk.add(fd), pk.add(ft), pk.add(bd), pk.add(bt), (int)fd.size(), (int)bd.size()});
         if (apply32) host_phases[li].push_back({fd, bd, ft, bt});
+      }
+      char *base = send(pk, persist, s);
+      for (const Offs &o : offs) {
+        SolvePhase<T> ph;
+        ph.f = at<GemvDesc<T>>(base, o.f);
+        ph.ft = at<GemvTerm<T>>(base, o.ft);
+        ph.nf = o.nf;
+        ph.b = at<GemvDesc<T>>(base, o.b);
+        ph.bt = at<GemvTerm<T>>(base, o.bt);
+        ph.nb = o.nb;
+        plist.push_back(ph);
       }
     }
     SBIE_HIP(hipStreamSynchronize(s));
