@@ -157,6 +157,18 @@ struct HTree {
   std::vector<std::vector<int64_t>> leaf_dofs;
 };
 
+// LSD radix sort of the low `bits` bits (8 per pass) of 64-bit keys.
+void radix_sort(std::vector<uint64_t> &a, int bits) {
+  std::vector<uint64_t> b(a.size());
+  for (int sh = 0; sh < bits; sh += 8) {
+    size_t cnt[257] = {0};
+    for (uint64_t x : a) ++cnt[((x >> sh) & 255) + 1];
+    for (int i = 0; i < 256; ++i) cnt[i + 1] += cnt[i];
+    for (uint64_t x : a) b[cnt[(x >> sh) & 255]++] = x;
+    a.swap(b);
+  }
+}
+
 HTree build_tree(const std::vector<double> &px, const std::vector<double> &py, int64_t nn,
                  int64_t wall_start, int leaf_target, int max_depth) {
   HTree t;
@@ -171,15 +183,38 @@ HTree build_tree(const std::vector<double> &px, const std::vector<double> &py, i
   t.size = ext * (1.0 + 1e-9) + 1e-12;
   t.x0 = lx - 1e-12 * t.size;
   t.y0 = ly - 1e-12 * t.size;
+  // Integer box coordinates at the finest admissible depth kTreeMax: the box
+  // of a point at depth d is (ax >> (kTreeMax - d), ay >> (kTreeMax - d)),
+  // exactly the floor of its coordinate over that level's side (the sides
+  // are the root side over powers of two, so the quotients scale exactly).
+  // Points are sorted once by the Morton code of that finest box; every
+  // level's boxes are then the distinct code prefixes, already in Morton
+  // order, with no hashing of points.
+  constexpr int kTreeMax = 20;
+  const double hmin = t.size / std::ldexp(1.0, kTreeMax);
+  if (np >= ((int64_t)1 << 24)) fail(SBIE_UNSUPPORTED, "too many points for the quadtree");
+  std::vector<uint32_t> ax(np), ay(np);
+  std::vector<uint64_t> code(np), node_code(nn);
+  for (int64_t i = 0; i < np; ++i) {
+    ax[i] = (uint32_t)std::floor((px[i] - t.x0) / hmin);
+    ay[i] = (uint32_t)std::floor((py[i] - t.y0) / hmin);
+    code[i] = (morton(ax[i], ay[i]) << 24) | (uint64_t)i;   // 40-bit code, 24-bit index
+    if (i < nn) node_code[i] = morton(ax[i], ay[i]);
+  }
+  radix_sort(code, 64);
+  radix_sort(node_code, 40);
   int depth = 1;
   while (true) {
-    const double h = t.size / std::ldexp(1.0, depth);
-    std::unordered_map<int64_t, int> seen;
-    for (int64_t i = 0; i < nn; ++i)
-      seen.emplace(key_of((int64_t)std::floor((px[i] - t.x0) / h),
-                          (int64_t)std::floor((py[i] - t.y0) / h)), 0);
-    if ((double)nn / (double)seen.size() <= leaf_target || (max_depth > 0 && depth >= max_depth) ||
-        depth >= 20)
+    const int sh = 2 * (kTreeMax - depth);
+    size_t distinct = 0;
+    uint64_t prev = ~0ull;
+    for (uint64_t c : node_code)
+      if ((c >> sh) != prev) {
+        ++distinct;
+        prev = c >> sh;
+      }
+    if ((double)nn / (double)distinct <= leaf_target || (max_depth > 0 && depth >= max_depth) ||
+        depth >= kTreeMax)
       break;
     ++depth;
   }
@@ -189,23 +224,23 @@ HTree build_tree(const std::vector<double> &px, const std::vector<double> &py, i
   for (int l = 0; l <= depth; ++l) {
     HLevel &L = t.lv[l];
     L.h = t.size / std::ldexp(1.0, l);
-    std::vector<std::pair<uint64_t, int64_t>> keys;
-    std::unordered_map<int64_t, std::pair<int64_t, int64_t>> kk;
-    for (int64_t i = 0; i < np; ++i) {
-      const int64_t ax = (int64_t)std::floor((px[i] - t.x0) / L.h);
-      const int64_t ay = (int64_t)std::floor((py[i] - t.y0) / L.h);
-      const int64_t k = key_of(ax, ay);
-      if (kk.emplace(k, std::make_pair(ax, ay)).second)
-        keys.emplace_back(morton((uint32_t)ax, (uint32_t)ay), k);
-    }
-    std::sort(keys.begin(), keys.end());
-    for (auto &e : keys) {
-      const auto xy = kk[e.second];
-      L.index[e.second] = (int)L.ix.size();
-      L.ix.push_back(xy.first);
-      L.iy.push_back(xy.second);
-      L.cx.push_back(t.x0 + (xy.first + 0.5) * L.h);
-      L.cy.push_back(t.y0 + (xy.second + 0.5) * L.h);
+    // the level's code prefix (level 0: a single box; a shift by 64 bits
+    // would be undefined)
+    const int sh = 2 * (kTreeMax - l) + 24, cs = kTreeMax - l;
+    uint64_t prev = ~0ull;
+    for (uint64_t c : code) {
+      const int64_t i = (int64_t)(c & 0xffffff);
+      const uint64_t pre = sh >= 64 ? 0 : c >> sh;
+      if (pre != prev) {
+        prev = pre;
+        const int64_t bx = ax[i] >> cs, by = ay[i] >> cs;
+        L.index[key_of(bx, by)] = (int)L.ix.size();
+        L.ix.push_back(bx);
+        L.iy.push_back(by);
+        L.cx.push_back(t.x0 + (bx + 0.5) * L.h);
+        L.cy.push_back(t.y0 + (by + 0.5) * L.h);
+      }
+      if (l == depth) leaf_box[i] = L.size() - 1;
     }
     const int nb = L.size();
     L.nbrs.resize(nb);
@@ -220,10 +255,6 @@ HTree build_tree(const std::vector<double> &px, const std::vector<double> &py, i
     L.parent.assign(nb, -1);
     L.children.assign(nb, {});
     L.ilist.assign(nb, {});
-    if (l == depth)
-      for (int64_t i = 0; i < np; ++i)
-        leaf_box[i] = L.index[key_of((int64_t)std::floor((px[i] - t.x0) / L.h),
-                                     (int64_t)std::floor((py[i] - t.y0) / L.h))];
   }
   for (int l = 1; l <= depth; ++l) {
     HLevel &L = t.lv[l], &P = t.lv[l - 1];
