@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--eps", type=float, default=1e-5)
-    ap.add_argument("--eps-fp32", type=float, default=1e-4,
+    ap.add_argument("--eps-fp32", type=float, default=2e-4,
                     help="IFMM tolerance of the FP32 factorisation (--pc all): FP32 "
                          "rounding in the elimination swamps tolerances much below this")
     ap.add_argument("--cheb-n", type=int, default=6)
