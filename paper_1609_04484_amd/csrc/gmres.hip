@@ -302,10 +302,10 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
   res->iters = total;
   res->status = status;
   res->rel_res_true = relres;
-  // the left-preconditioned residual of the paper's tables
+  // the left-preconditioned residual of the paper's tables; the loop always
+  // leaves by one of its two exits right after computing r = f - A x for
+  // the final x (compensated), so r is reused
   if (use_pc) {
-    matvec_run(g, x, r.p, SBIE_MV_FULL_ACCURATE, mw, s);
-    rsub<<<nb, 256, 0, s>>>(f, n, r.p);
     apply_pc(r.p, wv.p);
     norm(wv.p, hdev.p);
     apply_pc(f, wv.p);
