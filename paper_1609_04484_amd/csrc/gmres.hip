@@ -215,9 +215,14 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
   int hist_pos = 1;
   while (true) {
     // the true residual uses compensated sums: when the density is much
-    // larger than the data, plain FP64 sums cannot resolve tol ||f||
-    matvec_run(g, x, r.p, SBIE_MV_FULL_ACCURATE, mw, s);
-    rsub<<<nb, 256, 0, s>>>(f, n, r.p);
+    // larger than the data, plain FP64 sums cannot resolve tol ||f||.  From
+    // a zero start the first residual is f itself (A 0 = 0 exactly).
+    if (total == 0 && !p->use_x0) {
+      SBIE_HIP(hipMemcpyAsync(r.p, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      matvec_run(g, x, r.p, SBIE_MV_FULL_ACCURATE, mw, s);
+      rsub<<<nb, 256, 0, s>>>(f, n, r.p);
+    }
     norm(r.p, hdev.p);
     const double beta = host_scalar(hdev.p);
     if (!std::isfinite(beta)) fail(SBIE_BREAKDOWN, "residual is not finite");
