@@ -548,9 +548,11 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
   double *norms = reinterpret_cast<double *>(shraw);   // c
   double *dots = norms + d.c;                           // rmax
   T *q = reinterpret_cast<T *>(dots + d.rmax);          // m
-  __shared__ double red_v[kPgsWaves];
+  // red_v / red_i serve the pivot search, red_s the norm of the projected
+  // column: each is rewritten only after at least one barrier that follows
+  // every read of it, so neither needs a barrier of its own after the reads
+  __shared__ double red_v[kPgsWaves], red_s[kPgsWaves];
   __shared__ int red_i[kPgsWaves];
-  __shared__ int s_stop;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = wv; j < d.c; j += kPgsWaves) {
     const T *col = d.R + (size_t)j * d.ldr;
@@ -581,7 +583,6 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
     int p = red_i[0];
     for (int w = 1; w < kPgsWaves; ++w)
       if (red_v[w] > vmax || (red_v[w] == vmax && red_i[w] < p)) { vmax = red_v[w]; p = red_i[w]; }
-    __syncthreads();
     if (!(vmax > tol2)) break;
     for (int i = tid; i < d.m; i += kPgsThreads) q[i] = d.R[i + (size_t)p * d.ldr];
     __syncthreads();
@@ -606,13 +607,12 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
     double sq = 0.0;
     for (int i = tid; i < d.m; i += kPgsThreads) sq = fma((double)q[i], (double)q[i], sq);
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
-    if (lane == 0) red_v[wv] = sq;
+    if (lane == 0) red_s[wv] = sq;
     __syncthreads();
+    // every thread sums the same values in the same order: a uniform decision
     double nq = 0.0;
-    for (int w = 0; w < kPgsWaves; ++w) nq += red_v[w];
-    if (tid == 0) s_stop = (nq <= 1e-4 * vmax || !(nq > 0.0)) ? 1 : 0;
-    __syncthreads();
-    if (s_stop) {
+    for (int w = 0; w < kPgsWaves; ++w) nq += red_s[w];
+    if (nq <= 1e-4 * vmax || !(nq > 0.0)) {
       // numerically inside the current span: retire the column
       if (tid == 0) norms[p] = 0.0;
       __syncthreads();
