@@ -548,15 +548,17 @@ def _pad(m, r, c):
 
 def _augment(w: np.ndarray, cands, eps: float) -> np.ndarray:
     """Recompression: W_new = [W, Q] where Q spans the part of the
-    candidates outside span(W); each candidate block is truncated relative
-    to its own largest singular value (relative eps)."""
+    candidates outside span(W); each candidate block is first scaled by its
+    Frobenius norm (relative eps; the norm is the reading recorded for the
+    relative truncation of Section 3.3, the same on the GPU), then directions
+    with singular value <= eps are dropped."""
     if not cands:
         return w
     parts = []
     for c in cands:
         if c.size == 0:
             continue
-        s0 = np.linalg.norm(c, 2)
+        s0 = np.linalg.norm(c)
         if s0 == 0:
             continue
         parts.append(c / s0)
