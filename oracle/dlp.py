@@ -153,9 +153,14 @@ def assemble(geom, chunk: int = 2048) -> np.ndarray:
     return a
 
 
-def block(geom, rows, cols) -> np.ndarray:
-    """A[rows, cols] (computed from whole rows; small blocks only)."""
-    return rows_of_matrix(geom, rows)[:, np.asarray(cols, dtype=np.int64)]
+def block(geom, rows, cols, chunk: int = 256) -> np.ndarray:
+    """A[rows, cols], computed from whole rows ``chunk`` rows at a time."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    out = np.empty((rows.shape[0], cols.shape[0]))
+    for s in range(0, rows.shape[0], chunk):
+        out[s:s + chunk] = rows_of_matrix(geom, rows[s:s + chunk])[:, cols]
+    return out
 
 
 def apply(geom, u: np.ndarray, chunk: int = 1024) -> np.ndarray:

@@ -70,12 +70,15 @@ class GmresResult:
 
 
 def fgmres(matvec, f: np.ndarray, precond=None, x0=None, tol: float = 1e-10,
-           max_iter: int = 2000, restart: int | None = None) -> GmresResult:
+           max_iter: int = 2000, restart: int | None = None, residual=None,
+           log=None) -> GmresResult:
     """Flexible GMRES (right preconditioning), CGS2 Arnoldi.
 
     Stops when the (recurrence) residual falls to tol * ||F||, then checks the
     true residual and restarts from the current iterate if it is still above
-    the tolerance and iterations remain.
+    the tolerance and iterations remain.  ``residual(x)``, if given, computes
+    the true residual F - A x (for instance in extended precision); otherwise
+    it is F - matvec(x).  ``log(iters, estimate)`` is called after each step.
     """
     n = f.shape[0]
     restart = max_iter if restart is None else restart
@@ -86,7 +89,7 @@ def fgmres(matvec, f: np.ndarray, precond=None, x0=None, tol: float = 1e-10,
     hist = []
     total = 0
     while True:
-        r = f - matvec(x)
+        r = residual(x) if residual is not None else f - matvec(x)
         beta = np.linalg.norm(r)
         hist.append(beta / fnorm)
         if beta <= tol * fnorm or total >= max_iter:
@@ -127,6 +130,8 @@ def fgmres(matvec, f: np.ndarray, precond=None, x0=None, tol: float = 1e-10,
             total += 1
             k_used = j + 1
             hist.append(abs(g[j + 1]) / fnorm)
+            if log is not None:
+                log(total, hist[-1])
             if abs(g[j + 1]) <= tol * fnorm or breakdown or total >= max_iter:
                 break
         y = sla.solve_triangular(h[:k_used, :k_used], g[:k_used])
