@@ -49,6 +49,102 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, f, bd_iters):
+    """The CPU oracle's block-diagonal FGMRES solve of the same pipe, timed
+    on this host's cores by its parts (a bounded sample of ~20-40 s):
+
+    * one whole oracle operator application (plain C, every host core);
+    * the block-diagonal factor: assembly (NumPy oracle) and LAPACK LU of a
+      sample of pore blocks, scaled by the pore count, plus the assembly of
+      one 256-row slice of the wall block (scaled by the slices) and one LU
+      of a matrix of the wall block's order (LAPACK's time does not depend
+      on the values);
+    * one application of the factors: LU solves of the sampled pore blocks
+      (scaled) and of the wall-order factor;
+    * the CGS2 Arnoldi step at the mean Krylov dimension of the solve.
+
+    solves/s = 1 / (factor + iterations x (operator + apply + Arnoldi)), with
+    the iteration count the same algorithm needs for this pipe on the GPU."""
+    import scipy.linalg as sla
+    import threadpoolctl
+    from oracle import capply, dlp, solve
+    n = g.n_unknowns
+    x = np.random.default_rng(3).standard_normal(n)
+    capply._load()          # compile (if needed) and load the C oracle
+    t0 = time.perf_counter()
+    capply.apply(g, x)
+    t_mv = time.perf_counter() - t0
+    blocks = solve.bd_block_indices(g)
+    pores, wall = blocks[:-1], blocks[-1]
+    ks = list(range(0, len(pores), max(1, len(pores) // 8)))[:8]
+    t0 = time.perf_counter()
+    facs = [sla.lu_factor(dlp.block(g, pores[k], pores[k])) for k in ks]
+    t_pf = (time.perf_counter() - t0) * len(pores) / max(1, len(ks))
+    t0 = time.perf_counter()
+    dlp.block(g, wall[:256], wall)
+    t_wa = (time.perf_counter() - t0) * len(wall) / 256.0
+    w = np.random.default_rng(4).standard_normal((len(wall), len(wall)))
+    w[np.diag_indices_from(w)] += len(wall)
+    t0 = time.perf_counter()
+    wf = sla.lu_factor(w, overwrite_a=True, check_finite=False)
+    t_wl = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for fac, k in zip(facs, ks):
+        sla.lu_solve(fac, x[pores[k]])
+    t_pa = (time.perf_counter() - t0) * len(pores) / max(1, len(ks))
+    t0 = time.perf_counter()
+    sla.lu_solve(wf, x[wall])
+    t_wap = time.perf_counter() - t0
+    j = max(1, int(bd_iters / 2))
+    v = np.random.default_rng(5).standard_normal((j + 1, n))
+    t0 = time.perf_counter()
+    hj = v @ x
+    y = x - hj @ v
+    hj2 = v @ y
+    y = y - hj2 @ v
+    t_ar = time.perf_counter() - t0
+    t_factor = t_pf + t_wa + t_wl
+    t_iter = t_mv + t_pa + t_wap + t_ar
+    t_solve = t_factor + bd_iters * t_iter
+    blas = threadpoolctl.threadpool_info()
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(omp), "kind": "oracle",
+            "sample": (f"measured on this host ({cpu_model()}, nproc {os.cpu_count()}, "
+                       f"{omp} OpenMP threads, BLAS {blas[0]['internal_api'] if blas else 'n/a'} "
+                       f"x{blas[0]['num_threads'] if blas else 'n/a'}): oracle operator "
+                       f"{t_mv:.2f}s per application (whole, plain C); block-diagonal factor "
+                       f"{t_factor:.1f}s ({len(ks)} of {len(pores)} pore blocks and 256 of "
+                       f"{len(wall)} wall rows assembled and scaled, one {len(wall)}-order LU); "
+                       f"factor application {t_pa + t_wap:.3f}s; CGS2 at dimension {j} "
+                       f"{t_ar:.3f}s; x {bd_iters:.0f} iterations (the block-diagonal "
+                       f"solve's count on the GPU) = {t_solve:.0f}s per solve"),
+            "t_matvec_s": t_mv, "t_factor_s": t_factor, "t_iteration_s": t_iter,
+            "iterations": bd_iters}
+
+
+def recorded_oracle_solve(workload, seed):
+    """The whole oracle solve that wrote the stored reference solution of
+    this pipe (tests/golden/make_sigma.py), as recorded when it ran."""
+    path = os.path.join(ROOT, "tests", "golden", f"sigma_{workload}_s{seed}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        meta = json.load(fh)
+    return {k: meta.get(k) for k in ("method", "iters", "wall_s", "final_rel_residual_80bit",
+                                      "host_cpu", "host_cores")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +267,7 @@ def main():
         lib.kernel_timing(True)
         lib.kernel_time()
         iters, relres, relpc, tmv, tpc, tar, tfac, tstep = [], [], [], [], [], [], [], []
+        first_sigma = None
         t0 = time.perf_counter()
         for k in range(args.steps):
             dgk, fdk = dgeoms[k % len(dgeoms)], frhs[k % len(dgeoms)]
@@ -183,6 +280,8 @@ def main():
             tstep.append(time.perf_counter() - tf0)
             stats = pc.stats() if kind != "bd" else None
             pc.close()
+            if k == 0:
+                first_sigma = r.sigma      # the first pipe's solution (seed args.seed)
             iters.append(r.iters)
             relres.append(r.rel_res_true)
             relpc.append(r.rel_res_pc)
@@ -193,8 +292,7 @@ def main():
         elapsed = time.perf_counter() - t0
         lib.kernel_timing(False)
         kms, kcount = lib.kernel_time()
-        sigma = r.sigma
-        sigmas[kind] = sigma
+        sigmas[kind] = first_sigma
         results[kind] = dict(
             solves_per_s=args.steps / elapsed, ms_per_solve=1e3 * elapsed / args.steps,
             s_per_solve_median=float(np.median(tstep)), s_per_solve_min=float(np.min(tstep)),
@@ -204,6 +302,8 @@ def main():
             converged=all(x <= args.tol for x in relres),
             t_matvec_s=float(np.mean(tmv)), t_precond_apply_s=float(np.mean(tpc)),
             t_arnoldi_s=float(np.mean(tar)), t_factor_s=float(np.mean(tfac)),
+            t_factor_steps_s=[round(float(t), 4) for t in tfac],
+            t_step_s=[round(float(t), 4) for t in tstep],
             ifmm_stats=stats,
             pair_kernel_ms=kms / max(kcount, 1), pair_kernel_launches=kcount)
         log(f"[bench] {kind}: {results[kind]}")
@@ -233,14 +333,22 @@ def main():
     head = max(ifmm_kinds, key=lambda k: results[k]["solves_per_s"]) if ifmm_kinds else "bd"
     hr = results[head]
 
-    # sampled-row check of the last solution against the oracle's rows (the
-    # last step's pipe; every kind ends on the same one)
-    last = (args.steps - 1) % len(dgeoms)
-    g, f = geoms[last], rhs[last]
+    # every kind's solution of the first pipe against the oracle: the stored
+    # oracle solution sigma* (written by tests/golden/make_sigma.py from the
+    # CPU oracle alone) where it exists for this pipe, and the residual of the
+    # headline solution in 64 sampled rows of the oracle's matrix
+    g, f = geoms[0], rhs[0]
     from oracle import dlp
+    gold = os.path.join(ROOT, "tests", "golden", f"sigma_{args.workload}_s{seeds[0]}.npy")
+    if os.path.exists(gold):
+        sig_ref = np.load(gold, allow_pickle=False)
+        for k in results:
+            s_k = sigmas[k].cpu().numpy()
+            results[k]["rel_err_vs_oracle"] = float(np.linalg.norm(s_k - sig_ref)
+                                                    / np.linalg.norm(sig_ref))
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(n, 64, replace=False))
-    s_host = sigma.cpu().numpy()
+    s_host = sigmas[head].cpu().numpy()
     row_res = float(np.abs(dlp.apply_rows(g, s_host, rows) - f[rows]).max() / np.abs(f).max())
 
     # dominant kernel: the matvec pair kernel (FP64 vector ALU bound)
@@ -254,25 +362,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import threadpoolctl
-        sample = min(args.cpu_rows, n)
-        rows = np.sort(np.random.default_rng(2).choice(n, sample, replace=False))
-        x = np.random.default_rng(3).standard_normal(n)
-        t0 = time.perf_counter()
-        for s0 in range(0, sample, 64):
-            dlp.apply_rows(g, x, rows[s0:s0 + 64])
-        t_rows = time.perf_counter() - t0
-        t_mv_cpu = t_rows * n / sample
-        mv_per_solve = float(np.mean(results["bd"]["iters"] if "bd" in results else hr["iters"])) + 2
-        blas = threadpoolctl.threadpool_info()
-        cpu = {"value": 1.0 / (t_mv_cpu * mv_per_solve), "unit": "solves/s", "cores": 1,
-               "kind": "oracle",
-               "sample": (f"oracle matvec rows ({sample} of {n} rows, {t_rows:.1f}s, "
-                          f"single-threaded NumPy; BLAS threads "
-                          f"{blas[0]['num_threads'] if blas else 'n/a'}) scaled to a full "
-                          f"matvec ({t_mv_cpu:.1f}s) x {mv_per_solve:.0f} matvecs per "
-                          f"block-diagonal solve; preconditioner and Arnoldi excluded, so "
-                          f"this is an upper bound on CPU solves/s")}
+        bd_iters = float(np.mean(results["bd"]["iters"])) if "bd" in results else 1000.0
+        cpu = cpu_baseline(g, f, bd_iters)
+        cpu["full_oracle_solve_recorded"] = recorded_oracle_solve(args.workload, seeds[0])
         log(f"[bench] cpu baseline: {cpu}")
 
     stored = None

@@ -96,6 +96,24 @@ typedef struct {
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *sbie_last_error(void);
 
+/* Checks that a geometry describes what the operator assumes (Section 2:
+ * a closed outer wall enclosing disjoint circular pores; Section 2.2:
+ * distinct trapezoid nodes on every curve), on the device:
+ *   - every node: finite data, weight > 0, |n| = 1 (to 1e-8);
+ *   - every pore node at distance radius[k] from (cx[k], cy[k]) (to 1e-8
+ *     relative in the squared distance);
+ *   - no node repeated on its own curve;
+ *   - pores pairwise disjoint (centre distance > sum of radii), finite
+ *     centres, radius > 0;
+ *   - every pore centre inside the wall polygon and every wall node
+ *     outside every pore disc (skipped when there is no wall).
+ * Synchronises the stream.  Returns SBIE_OK or SBIE_INVALID_GEOMETRY (the
+ * message names every violated condition); SBIE_INVALID_ARGUMENT for a bad
+ * descriptor.  gmres_solve, bd_factor, ifmm_factor and the batched solver
+ * entry points run the same checks before any other work; the matvec and
+ * the assembly do not (they are the inner products of a solve). */
+int sbie_validate_geometry(const sbie_geom *g, void *stream);
+
 /* Entries A[rows, cols] of the operator above (Section 2.2, equation
  * "f = A sigma"), for arbitrary global row and column indices.
  *   rows   device int64[nr], each in [0, n).

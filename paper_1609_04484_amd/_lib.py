@@ -94,6 +94,7 @@ class GmresMember(ctypes.Structure):
 
 EXPORTS = {
     "sbie_last_error": (ctypes.c_char_p, []),
+    "sbie_validate_geometry": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp]),
     "stokes_bie_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, ctypes.c_int64,
                                            _c_dp, ctypes.c_int64, _c_dp, ctypes.c_int64, _c_dp]),
     "stokes_dlp_matvec": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int, _c_dp]),
@@ -216,6 +217,11 @@ class DeviceGeometry:
 
     def vector(self, a) -> torch.Tensor:
         return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.t["x"].device).contiguous()
+
+
+def validate(dg: DeviceGeometry, stream=None):
+    """Device-side geometry checks; raises SbieError(INVALID_GEOMETRY)."""
+    check(load().sbie_validate_geometry(ctypes.byref(dg.c), _stream(stream)))
 
 
 def matvec(dg: DeviceGeometry, x: torch.Tensor, mode: int = 0, out=None, stream=None):

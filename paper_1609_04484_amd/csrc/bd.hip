@@ -3,6 +3,7 @@
 // wall, each assembled on the device and inverted exactly.  Applying it is
 // one batched block GEMV for the pores and one split-K GEMV for the wall.
 #include "assemble.hpp"
+#include "batched.hpp"
 #include "dense.hpp"
 
 struct sbie_bd {
@@ -76,8 +77,20 @@ void bd_build(const sbie_geom *g, sbie_bd *bd, hipStream_t s) {
     SBIE_HIP(hipMemcpyAsync(bd->widx.p, widx.data(), widx.size() * 8, hipMemcpyHostToDevice, s));
     bd->wmat.alloc((size_t)bd->nwall * bd->nwall);
     assemble_block(v, bd->widx.p, bd->nwall, bd->widx.p, bd->nwall, bd->wmat.p, bd->nwall, s);
-    DenseWork dw;
-    blocked_inverse_nopivot(bd->wmat.p, bd->nwall, 128, s, dw);
+    if (bd->nwall > 8192)
+      fail(SBIE_UNSUPPORTED, "wall block of order %lld exceeds 8192", (long long)bd->nwall);
+    // blocked Gauss-Jordan with partial pivoting by columns; its rank-32
+    // updates run on the FP64 matrix-core GEMM tiles (the descriptors of
+    // all panel steps are staged in one transfer)
+    {
+      Stager st((size_t)48 << 20);
+      DevBuf<int32_t> winfo(1);
+      inverse_batched_blocked<double>({bd->wmat.p}, {(int)bd->nwall}, winfo.p, st, s);
+      int32_t hw = 0;
+      SBIE_HIP(hipMemcpyAsync(&hw, winfo.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      SBIE_HIP(hipStreamSynchronize(s));
+      if (hw != 0) fail(SBIE_BREAKDOWN, "wall block is singular (pivot %d)", (int)hw);
+    }
     bd->wch = (int)((bd->nwall + 255) / 256);
     if (bd->wch > 64) bd->wch = 64;
     bd->wpart.alloc((size_t)bd->wch * bd->nwall);
@@ -102,6 +115,7 @@ extern "C" int bd_factor(const sbie_geom *g, sbie_bd **out, void *stream) {
     sbie::validate_geom(g);
     if (!out) sbie::fail(SBIE_INVALID_ARGUMENT, "null output handle");
     *out = nullptr;
+    sbie::validate_geom_device(g, (hipStream_t)stream);
     auto *bd = new sbie_bd();
     try {
       sbie::bd_build(g, bd, (hipStream_t)stream);

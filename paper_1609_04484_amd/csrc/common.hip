@@ -1,4 +1,4 @@
-// Error plumbing, descriptor validation and the per-device rocBLAS handle.
+// Error plumbing and descriptor validation.
 #include <cmath>
 #include <mutex>
 
@@ -8,21 +8,9 @@ namespace sbie {
 
 namespace {
 thread_local std::string g_last_error;
-std::mutex g_blas_mu;
-std::vector<rocblas_handle> g_blas;  // one per device, created on first use
 }  // namespace
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
-
-rocblas_handle blas_handle(hipStream_t stream) {
-  int dev = 0;
-  SBIE_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  if ((int)g_blas.size() <= dev) g_blas.resize(dev + 1, nullptr);
-  if (!g_blas[dev]) SBIE_BLAS(rocblas_create_handle(&g_blas[dev]));
-  SBIE_BLAS(rocblas_set_stream(g_blas[dev], stream));
-  return g_blas[dev];
-}
 
 void validate_geom(const sbie_geom *g) {
   if (!g) fail(SBIE_INVALID_ARGUMENT, "null geometry descriptor");

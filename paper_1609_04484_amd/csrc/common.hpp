@@ -1,10 +1,9 @@
 // Internal helpers shared by the library's translation units: status and
-// error-message plumbing, HIP error checks, small RAII device buffers, the
-// per-device rocBLAS handle and the geometry-derived constants.
+// error-message plumbing, HIP error checks, small RAII device buffers and
+// the geometry-derived constants.
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <cstdarg>
 #include <cstdint>
@@ -42,14 +41,6 @@ void set_last_error(const std::string &msg);
     if (e_ != hipSuccess)                                                     \
       ::sbie::fail(SBIE_HIP_ERROR, "%s failed: %s (%s:%d)", #call,            \
                    hipGetErrorString(e_), __FILE__, __LINE__);                \
-  } while (0)
-
-#define SBIE_BLAS(call)                                                       \
-  do {                                                                        \
-    rocblas_status s_ = (call);                                               \
-    if (s_ != rocblas_status_success)                                         \
-      ::sbie::fail(SBIE_HIP_ERROR, "%s failed: rocblas status %d (%s:%d)",    \
-                   #call, (int)s_, __FILE__, __LINE__);                       \
   } while (0)
 
 #define SBIE_LAUNCH_CHECK() SBIE_HIP(hipGetLastError())
@@ -125,10 +116,13 @@ struct StreamBuf {
   }
 };
 
-rocblas_handle blas_handle(hipStream_t stream);
-
 // Checks on the geometry descriptor that need no device access.
 void validate_geom(const sbie_geom *g);
+// validate_geom plus the device-side checks of the node and pore data
+// (finite values, unit normals, pore nodes on their circles, no repeated
+// node, disjoint pores strictly inside the wall); synchronises the stream
+// and fails with SBIE_INVALID_GEOMETRY naming the violated conditions.
+void validate_geom_device(const sbie_geom *g, hipStream_t s);
 
 inline int64_t n_unknowns(const sbie_geom *g) {
   return 2 * g->n_nodes + 3 * (int64_t)g->n_pores;
@@ -142,7 +136,7 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 struct MatvecWork {
   double *src = nullptr;     // packed source records, 8 doubles per node
   double *psrc = nullptr;    // packed pore records, 8 doubles per pore
-  double *part = nullptr;    // partial sums [chunks][2][Nn]
+  double *part = nullptr;    // partial sums [chunks + pchunks][2 or 4][Nn]
   double *scal = nullptr;    // [0] = flux functional, [1] = wall length
   int chunks = 0;            // source chunks of the pair kernel
   int pchunks = 0;           // pore chunks of the completion kernel

@@ -1,8 +1,7 @@
-// Dense kernels for the preconditioners: batched in-place Gauss-Jordan
-// inversion with partial pivoting (one workgroup per matrix), a blocked
-// Gauss-Jordan inversion for large well-conditioned blocks whose rank-nb
-// updates are plain GEMMs (rocBLAS, FP64 MFMA), and block-diagonal
-// matrix-vector products.
+// Dense kernels for the block-diagonal preconditioner: batched in-place
+// Gauss-Jordan inversion with partial pivoting (one workgroup per matrix)
+// and block-diagonal matrix-vector products.  (The large wall block is
+// inverted by the blocked inverse of batched.hip.)
 #include "dense.hpp"
 
 namespace sbie {
@@ -98,24 +97,6 @@ __global__ __launch_bounds__(kGJ) void gj_inverse_kernel(
   if (tid == 0) info[b] = 0;
 }
 
-// dst (rows x cols, ld_dst) = src (rows x cols, ld_src); optionally zero the
-// source rows [z0, z1) in the copy.
-__global__ void copy_block(const double *__restrict__ src, int64_t ld_src,
-                           double *__restrict__ dst, int64_t ld_dst,
-                           int64_t rows, int64_t cols, int64_t z0, int64_t z1) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = blockIdx.y;
-  if (i >= rows || j >= cols) return;
-  dst[i + j * ld_dst] = (i >= z0 && i < z1) ? 0.0 : src[i + j * ld_src];
-}
-
-__global__ void zero_block(double *__restrict__ dst, int64_t ld, int64_t rows,
-                           int64_t cols) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = blockIdx.y;
-  if (i < rows && j < cols) dst[i + j * ld] = 0.0;
-}
-
 // out[idx[r]] = sum_c M[r + c n] v[idx[c]], one workgroup per block.
 __global__ __launch_bounds__(256) void block_gemv_small(
     const double *__restrict__ mats, const int64_t *__restrict__ moff,
@@ -170,62 +151,6 @@ void gj_inverse_batched(double *base, const int64_t *off, const int32_t *sz,
     fail(SBIE_UNSUPPORTED, "batched inverse limited to n <= 2560 (got %d)", max_n);
   gj_inverse_kernel<<<nmat, kGJ, shmem, s>>>(base, off, sz, info);
   SBIE_LAUNCH_CHECK();
-}
-
-void copy_submatrix(const double *src, int64_t ld_src, double *dst,
-                    int64_t ld_dst, int64_t rows, int64_t cols, hipStream_t s,
-                    int64_t zero_r0, int64_t zero_r1) {
-  if (rows == 0 || cols == 0) return;
-  dim3 grid(ceil_div(rows, 256), (unsigned)cols);
-  copy_block<<<grid, 256, 0, s>>>(src, ld_src, dst, ld_dst, rows, cols, zero_r0, zero_r1);
-  SBIE_LAUNCH_CHECK();
-}
-
-void blocked_inverse_nopivot(double *M, int64_t n, int nb, hipStream_t s,
-                             DenseWork &w) {
-  rocblas_handle h = blas_handle(s);
-  if ((int64_t)w.C.n < n * nb) w.C.alloc(n * nb);
-  if ((int64_t)w.R.n < n * nb) w.R.alloc(n * nb);
-  if ((int64_t)w.P.n < (int64_t)nb * nb) w.P.alloc((size_t)nb * nb);
-  if (w.meta.n < 4) w.meta.alloc(4);
-  int64_t meta_host[2] = {0, 0};
-  int32_t hinfo = 0;
-  for (int64_t p0 = 0; p0 < n; p0 += nb) {
-    const int pb = (int)(n - p0 < nb ? n - p0 : nb);
-    // P = M_pp^{-1}
-    copy_submatrix(M + p0 + p0 * n, n, w.P.p, pb, pb, pb, s);
-    meta_host[0] = 0;
-    int32_t szh = pb;
-    SBIE_HIP(hipMemcpyAsync(w.meta.p, meta_host, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    SBIE_HIP(hipMemcpyAsync(reinterpret_cast<int32_t *>(w.meta.p + 1), &szh, sizeof(int32_t),
-                            hipMemcpyHostToDevice, s));
-    gj_inverse_batched(w.P.p, w.meta.p, reinterpret_cast<int32_t *>(w.meta.p + 1), 1, pb,
-                       reinterpret_cast<int32_t *>(w.meta.p + 2), s);
-    SBIE_HIP(hipMemcpyAsync(&hinfo, reinterpret_cast<int32_t *>(w.meta.p + 2), sizeof(int32_t),
-                            hipMemcpyDeviceToHost, s));
-    SBIE_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) fail(SBIE_BREAKDOWN, "singular diagonal tile at row %lld", (long long)p0);
-    // C = M[:, p] with the pivot rows zeroed
-    copy_submatrix(M + p0 * n, n, w.C.p, n, n, pb, s, p0, p0 + pb);
-    // R = P M[p, :], with its pivot columns zeroed
-    const double one = 1.0, zero = 0.0, mone = -1.0;
-    SBIE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, pb, n, pb,
-                            &one, w.P.p, pb, M + p0, n, &zero, w.R.p, pb));
-    {
-      dim3 grid(ceil_div(pb, 256), (unsigned)pb);
-      zero_block<<<grid, 256, 0, s>>>(w.R.p + p0 * pb, pb, pb, pb);
-      SBIE_LAUNCH_CHECK();
-    }
-    // M -= C R   (rows and columns outside the pivot block)
-    SBIE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, pb,
-                            &mone, w.C.p, n, w.R.p, pb, &one, M, n));
-    // M[p, :] = R
-    copy_submatrix(w.R.p, pb, M + p0, n, pb, n, s);
-    // M[:, p] = -C P, then M_pp = P
-    SBIE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, pb, pb,
-                            &mone, w.C.p, n, w.P.p, pb, &zero, M + p0 * n, n));
-    copy_submatrix(w.P.p, pb, M + p0 + p0 * n, n, pb, pb, s);
-  }
 }
 
 void block_gemv(const double *mats, const int64_t *moff_dev, const int64_t *idx,

@@ -342,6 +342,7 @@ extern "C" int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
     if (p->pc < 0 || p->pc > 2) sbie::fail(SBIE_INVALID_ARGUMENT, "unknown preconditioner %d", p->pc);
     const int64_t n = sbie::n_unknowns(g);
     if (f < sigma + n && sigma < f + n) sbie::fail(SBIE_INVALID_ARGUMENT, "f and sigma overlap");
+    sbie::validate_geom_device(g, (hipStream_t)stream);
     *res = gmres_result{};
     return sbie::gmres_run(g, f, sigma, p, res, (hipStream_t)stream);
   });

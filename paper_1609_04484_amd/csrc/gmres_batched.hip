@@ -510,6 +510,7 @@ extern "C" int gmres_solve_batched(const sbie_geom *geoms, int32_t count, const 
       if (f[b] < sigma[b] + n && sigma[b] < f[b] + n)
         sbie::fail(SBIE_INVALID_ARGUMENT, "member %d: f and sigma overlap", b);
     }
+    for (int b = 0; b < count; ++b) sbie::validate_geom_device(&geoms[b], (hipStream_t)stream);
     return sbie::gmres_batched_run(geoms, count, f, sigma, members, tol, max_iter, restart, results,
                                    (hipStream_t)stream);
   });

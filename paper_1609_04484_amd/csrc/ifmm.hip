@@ -1600,6 +1600,7 @@ ifmm_handle *ifmm_factor_internal(const sbie_geom *g, const ifmm_params *p, hipS
                                   bool defer_graph) {
   validate_geom(g);
   if (!p) fail(SBIE_INVALID_ARGUMENT, "null pointer");
+  validate_geom_device(g, s);
   auto h = std::make_unique<ifmm_handle>();
   if (p->precision == 0 || p->precision == 2) {
     auto impl = std::make_unique<IfmmImpl<double>>();

@@ -3,13 +3,17 @@
 //
 // Launch structure of one y = A x:
 //   pack_sources      SoA node data + current density -> 64-byte source records
-//                     (x, y, w nx/pi, w ny/pi, sigma_x, sigma_y); pore records
+//                     (x, y, q_xx, q_xy, q_yy) with q the symmetric part of
+//                     a sigma^T, a = w n / pi, so that the pair factor
+//                     (r.a)(r.sigma) = r^T q r; pore records
 //                     (cx, cy, lambda_x, lambda_y, r mu)
 //   wall_flux         flux functional sum_wall w n.sigma and |Gamma_0|
 //   dlp_pairs<T>      the O(Nn^2) pair sum, split into (target tile, source
-//                     chunk) workgroups; each thread owns T targets; source
-//                     records are wave-uniform so they are read through the
-//                     scalar data path and broadcast, with no LDS traffic
+//                     chunk) workgroups; each lane owns T targets and the
+//                     four waves of a workgroup share the tile and split the
+//                     chunk, then add their sums in LDS (one partial sum per
+//                     workgroup); source records are wave-uniform so they
+//                     are read through the scalar data path and broadcast
 //   completion_pairs  Stokeslet/rotlet columns, (target tile, pore chunk)
 //   epilogue          sums the partials, adds the jump, the smooth diagonal
 //                     limit and the wall rank-one term
@@ -42,10 +46,11 @@ __device__ __forceinline__ void pack_body(int64_t j, int64_t nn, int m, const do
                                           double *__restrict__ src, double *__restrict__ psrc) {
   if (j < nn) {
     const double s = w[j] * (1.0 / kPi);
+    const double ax = s * nx[j], ay = s * ny[j], sx = u[j], sy = u[nn + j];
     double2 *d = reinterpret_cast<double2 *>(src + 8 * j);
     d[0] = make_double2(x[j], y[j]);
-    d[1] = make_double2(s * nx[j], s * ny[j]);
-    d[2] = make_double2(u[j], u[nn + j]);
+    d[1] = make_double2(ax * sx, fma(ax, sy, ay * sx));
+    d[2] = make_double2(ay * sy, 0.0);
     d[3] = make_double2(0.0, 0.0);
   }
   if (j < m) {
@@ -174,22 +179,24 @@ __device__ __forceinline__ void batch_recip(const double *d, double *out) {
 
 // The contribution of one source record to T targets, with the
 // reciprocals of S consecutive sources batched together (S * T values).
+// Per pair: r (2), r_y^2 and rho^2 (2), its share of the batched
+// reciprocal, r^T q r = r_x (q_xx r_x + q_xy r_y) + q_yy r_y^2 (4),
+// 1/rho^4 (1), the coefficient (1) and two accumulating FMAs.
 template <int T, int S, bool ACC>
 __device__ __forceinline__ void pair_step(const double *__restrict__ src, int j, const double *xi,
                                           const double *yi, double *ax, double *ay, double *cxa,
                                           double *cya) {
-  double sx[S], sy[S], sax[S], say[S], ssx[S], ssy[S];
+  double sx[S], sy[S], qxx[S], qxy[S], qyy[S];
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     const double *s = src + 8 * (int64_t)(j + q);  // wave-uniform: scalar loads
     sx[q] = s[0];
     sy[q] = s[1];
-    sax[q] = s[2];
-    say[q] = s[3];
-    ssx[q] = s[4];
-    ssy[q] = s[5];
+    qxx[q] = s[2];
+    qxy[q] = s[3];
+    qyy[q] = s[4];
   }
-  double rx[S * T], ry[S * T], r2[S * T], inv[S * T];
+  double rx[S * T], ry[S * T], ryy[S * T], r2[S * T], inv[S * T];
 #pragma unroll
   for (int q = 0; q < S; ++q)
 #pragma unroll
@@ -198,10 +205,11 @@ __device__ __forceinline__ void pair_step(const double *__restrict__ src, int j,
       rx[u] = xi[t] - sx[q];
       ry[u] = yi[t] - sy[q];
       // the self pair has r = 0 exactly: the 1e-100 added inside the fused
-      // multiply-add keeps 1/rho^4 finite there (the pair's factors
-      // (r.a)(r.sigma) are exactly zero) and is below half an ulp of rho^2
-      // for every other pair, so it changes no other result
-      r2[u] = fma(ry[u], ry[u], fma(rx[u], rx[u], 1e-100));
+      // multiply-add keeps 1/rho^4 finite there (the pair's factor r^T q r
+      // is then q_yy 1e-100, times r = 0) and is below half an ulp of
+      // r_y^2 and rho^2 for every pair of distinct nodes
+      ryy[u] = fma(ry[u], ry[u], 1e-100);
+      r2[u] = fma(rx[u], rx[u], ryy[u]);
     }
   batch_recip<S * T>(r2, inv);
 #pragma unroll
@@ -209,9 +217,9 @@ __device__ __forceinline__ void pair_step(const double *__restrict__ src, int j,
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const int u = q * T + t;
-      const double dn = fma(ry[u], say[q], rx[u] * sax[q]);
-      const double ds = fma(ry[u], ssy[q], rx[u] * ssx[q]);
-      const double c = (dn * ds) * (inv[u] * inv[u]);
+      const double h = fma(qxy[q], ry[u], qxx[q] * rx[u]);
+      const double pq = fma(h, rx[u], qyy[q] * ryy[u]);
+      const double c = pq * (inv[u] * inv[u]);
       if (ACC) {
         two_sum_acc(ax[t], cxa[t], c * rx[u]);
         two_sum_acc(ay[t], cya[t], c * ry[u]);
@@ -222,20 +230,30 @@ __device__ __forceinline__ void pair_step(const double *__restrict__ src, int j,
     }
 }
 
-// One workgroup of the pair sum: target tile `tile` (kBlock * T targets)
-// against source chunk `ch` (sources [ch * chunk, (ch + 1) * chunk)).  The
-// plain kernel takes two sources per step for T <= 4 (eight or fewer
-// reciprocals share one hardware reciprocal); the compensated one takes one.
+// One workgroup of the pair sum: target tile `tile` (64 T targets, lane l
+// owning targets tile * 64 T + l + 64 t) against source chunk `ch` (sources
+// [ch * chunk, (ch + 1) * chunk)), the chunk split into four consecutive
+// quarters, one per wave.  The plain kernel takes two sources per step for
+// T <= 4 (eight or fewer reciprocals share one hardware reciprocal); the
+// compensated one takes one.  The four waves' sums are added in LDS in a
+// fixed order and one partial sum per target is written:
+// part[ch][0..1 or 0..3][nn] (value x, y and, compensated, their errors).
+constexpr int kWaves = kBlock / 64;
+constexpr int kTileLanes = 64;
+
 template <int T, bool ACC>
 __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, const double *__restrict__ xs,
                                                const double *__restrict__ ys, int64_t nn, int64_t chunk,
                                                double *__restrict__ part, int64_t tile, int64_t ch) {
   constexpr int S = (!ACC && T <= 4) ? 2 : 1;
-  const int64_t tile0 = tile * (kBlock * T) + threadIdx.x;
+  constexpr int NV = ACC ? 4 : 2;    // values per target in a partial sum
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t tile0 = tile * (kTileLanes * T) + lane;
   double xi[T], yi[T], ax[T], ay[T], cxa[T], cya[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int64_t i = tile0 + (int64_t)t * kBlock;
+    const int64_t i = tile0 + (int64_t)t * kTileLanes;
     // padding targets of the last tile sit far away from every node and at
     // distinct places, so at most one target per thread can coincide with a
     // source (the batched reciprocal multiplies the squared distances)
@@ -247,16 +265,49 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
     cya[t] = 0.0;
   }
   // uniform 32-bit loop bounds kept in scalar registers (node counts are
-  // below 2^31), so the loop test is a scalar compare
-  const int j0 = __builtin_amdgcn_readfirstlane((int)(ch * chunk));
-  const int j1 = __builtin_amdgcn_readfirstlane((int)(ch * chunk + chunk < nn ? ch * chunk + chunk : nn));
+  // below 2^31), so the loop test is a scalar compare; this wave's quarter
+  // of the chunk
+  const int c0 = (int)(ch * chunk);
+  const int c1 = (int)(ch * chunk + chunk < nn ? ch * chunk + chunk : nn);
+  const int qlen = c1 > c0 ? (c1 - c0 + kWaves - 1) / kWaves : 0;
+  const int j0 = __builtin_amdgcn_readfirstlane(c0 + wv * qlen < c1 ? c0 + wv * qlen : c1);
+  const int j1 = __builtin_amdgcn_readfirstlane(j0 + qlen < c1 ? j0 + qlen : c1);
   const int js = j1 > j0 ? j0 + ((j1 - j0) / S) * S : j0;
   for (int j = j0; j < js; j += S) pair_step<T, S, ACC>(src, j, xi, yi, ax, ay, cxa, cya);
   for (int j = js; j < j1; ++j) pair_step<T, 1, ACC>(src, j, xi, yi, ax, ay, cxa, cya);
-  double *px = part + ch * 4 * nn;
+  // waves 1..3 hand their sums to wave 0 through LDS
+  __shared__ double red[kWaves - 1][NV * T][kTileLanes];
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      red[wv - 1][NV * t][lane] = ax[t];
+      red[wv - 1][NV * t + 1][lane] = ay[t];
+      if (ACC) {
+        red[wv - 1][NV * t + 2][lane] = cxa[t];
+        red[wv - 1][NV * t + 3][lane] = cya[t];
+      }
+    }
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int o = 0; o < kWaves - 1; ++o)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if (ACC) {
+        two_sum_acc(ax[t], cxa[t], red[o][NV * t][lane]);
+        two_sum_acc(ay[t], cya[t], red[o][NV * t + 1][lane]);
+        cxa[t] += red[o][NV * t + 2][lane];
+        cya[t] += red[o][NV * t + 3][lane];
+      } else {
+        ax[t] += red[o][NV * t][lane];
+        ay[t] += red[o][NV * t + 1][lane];
+      }
+    }
+  double *px = part + ch * NV * nn;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int64_t i = tile0 + (int64_t)t * kBlock;
+    const int64_t i = tile0 + (int64_t)t * kTileLanes;
     if (i < nn) {
       px[i] = ax[t];
       px[nn + i] = ay[t];
@@ -320,7 +371,7 @@ __device__ __forceinline__ void completion_body(const double *__restrict__ psrc,
     }
   }
   if (i0 < nn) {
-    double *px = part + (int64_t)pc * 4 * nn;
+    double *px = part + (int64_t)pc * (ACC ? 4 : 2) * nn;
     px[i0] = ax;
     px[nn + i0] = ay;
     if (ACC) {
@@ -355,8 +406,9 @@ __device__ __forceinline__ void epilogue_body(int64_t i, int64_t nn, int64_t wal
   auto add = [&](double &v, double &e, double a) {
     if (acc) two_sum_acc(v, e, a); else v += a;
   };
+  const int64_t stride = (acc ? 4 : 2) * nn;   // doubles per partial sum
   for (int c = 0; c < nchunks; ++c) {
-    const double *p = part + (int64_t)c * 4 * nn;
+    const double *p = part + (int64_t)c * stride;
     add(vx, ex, p[i]);
     add(vy, ey, p[nn + i]);
     if (acc) {
@@ -372,7 +424,7 @@ __device__ __forceinline__ void epilogue_body(int64_t i, int64_t nn, int64_t wal
   if (full) {
     double cx = 0.0, cy = 0.0, ecx = 0.0, ecy = 0.0;
     for (int c = 0; c < npchunks; ++c) {
-      const double *p = part + (int64_t)(nchunks + c) * 4 * nn;
+      const double *p = part + (int64_t)(nchunks + c) * stride;
       add(cx, ecx, p[i]);
       add(cy, ecy, p[nn + i]);
       if (acc) {
@@ -509,12 +561,12 @@ int64_t resident_pair_blocks(int tpt) {
 // Source chunks for the pair kernel.  All (tile, chunk) workgroups cost the
 // same; with few of them per resident slot the last, partly filled round of
 // workgroups is a large share of the run.  About eight rounds of the
-// device's resident workgroups keep that share small while the partial sums
-// (2 nn doubles per chunk, re-read by the epilogue) stay a few percent of
-// the pair time; chunks hold at least 128 sources.
+// device's resident workgroups keep that share small; the partial sums (2 nn
+// doubles per chunk, re-read by the epilogue) are then a few percent of the
+// pair time.  Chunks hold at least 256 sources (64 per wave).
 int choose_chunks(int64_t nn, int64_t tiles, int tpt) {
   const int64_t resident = resident_pair_blocks(tpt);
-  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((nn + 127) / 128, 1024));
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((nn + 255) / 256, 1024));
   const int64_t want = (8 * resident + tiles - 1) / tiles;
   int64_t c = std::max<int64_t>(1, std::min(want, cap));
   if (c >= 16) c &= ~int64_t(7);   // a multiple of 8 for the XCD-aware order
@@ -525,7 +577,7 @@ MatvecWork plan_matvec(const sbie_geom *g) {
   MatvecWork w;
   w.tpt = g_tpt;
   const int64_t nn = g->n_nodes;
-  const int64_t tiles = ceil_div(nn, (int64_t)kBlock * w.tpt);
+  const int64_t tiles = ceil_div(nn, (int64_t)kTileLanes * w.tpt);
   if (g_chunks > 0) {
     w.chunks = g_chunks;
   } else {
@@ -544,10 +596,12 @@ size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g) {
 
 void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
   const int64_t nn = g->n_nodes;
+  // records, then the two scalars, then the partial sums (their size
+  // depends on the mode and is last so that a smaller mode needs less)
   w.src = base;
   w.psrc = w.src + 8 * nn;
-  w.part = w.psrc + 8 * (g->n_pores + 1);
-  w.scal = w.part + (size_t)(w.chunks + w.pchunks) * 4 * nn;
+  w.scal = w.psrc + 8 * (g->n_pores + 1);
+  w.part = w.scal + 8;
 }
 
 void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
@@ -567,11 +621,12 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_LAUNCH_CHECK();
   }
   const int64_t chunk = (nn + w.chunks - 1) / w.chunks;
-  const int tiles = (int)ceil_div(nn, (int64_t)kBlock * w.tpt);
+  const int tiles = (int)ceil_div(nn, (int64_t)kTileLanes * w.tpt);
   const int xcd = (w.chunks % 8 == 0) ? 1 : 0;
   const unsigned grid = (unsigned)((int64_t)tiles * w.chunks);
-  const int tiles1 = (int)ceil_div(nn, kBlock);
+  const int tiles1 = (int)ceil_div(nn, kTileLanes);
   const unsigned grid1 = (unsigned)((int64_t)tiles1 * w.chunks);
+  const int64_t stride = (acc ? 4 : 2) * nn;   // doubles per partial sum
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // only the plain pair kernel is timed (the compensated one is a
   // different kernel, launched for true residuals)
@@ -600,10 +655,10 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     dim3 pg(ceil_div(nn, kBlock), w.pchunks);
     if (acc)
       completion_pairs<true><<<pg, kBlock, 0, s>>>(w.psrc, g->x, g->y, nn, m,
-                                                   w.part + (size_t)w.chunks * 4 * nn);
+                                                   w.part + (size_t)w.chunks * stride);
     else
       completion_pairs<false><<<pg, kBlock, 0, s>>>(w.psrc, g->x, g->y, nn, m,
-                                                    w.part + (size_t)w.chunks * 4 * nn);
+                                                    w.part + (size_t)w.chunks * stride);
     SBIE_LAUNCH_CHECK();
   }
   epilogue<<<ceil_div(nn, 256), 256, 0, s>>>(nn, wall_start, w.chunks,
@@ -673,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void completion_b(const BMember *__restrict
   const int b = find_member(st, nb, blockIdx.x);
   const BMember &M = d[b];
   const int64_t u = (int64_t)blockIdx.x - st[b];
-  completion_body<ACC>(M.psrc, M.x, M.y, M.nn, M.m, M.part + (int64_t)M.chunks * 4 * M.nn,
+  completion_body<ACC>(M.psrc, M.x, M.y, M.nn, M.m, M.part + (int64_t)M.chunks * (ACC ? 4 : 2) * M.nn,
                        u % M.ctiles, (int)(u / M.ctiles));
 }
 
@@ -751,7 +806,7 @@ void BatchMatvec::run(const std::vector<int> &members, const std::vector<const d
     M.pchunks = w.pchunks;
     M.pad = 0;
     M.chunk = (M.nn + w.chunks - 1) / w.chunks;
-    M.tiles = ceil_div(M.nn, (int64_t)kBlock * T);
+    M.tiles = ceil_div(M.nn, (int64_t)kTileLanes * T);
     M.ctiles = ceil_div(M.nn, kBlock);
     M.src = w.src; M.psrc = w.psrc; M.part = w.part; M.scal = w.scal;
     M.u = u[a];

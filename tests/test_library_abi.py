@@ -87,3 +87,17 @@ def test_argument_errors_without_gpu():
     assert lib.gmres_solve(None, None, None, None, None, None) == -1
     h = ctypes.c_void_p()
     assert lib.bd_factor(None, ctypes.byref(h), None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_uses_no_vendor_math_library():
+    """Every kernel of the hot path is the project's own: the library links
+    no BLAS/LAPACK/solver library and references none of their symbols."""
+    needed = subprocess.run(["readelf", "-d", LIB], capture_output=True, text=True,
+                            check=True).stdout
+    libs = re.findall(r"Shared library: \[([^\]]+)\]", needed)
+    banned = ("rocblas", "hipblas", "rocsolver", "hipsolver", "blaslt", "miopen", "rocfft")
+    assert not [n for n in libs if any(b in n.lower() for b in banned)], libs
+    undef = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True,
+                           text=True, check=True).stdout.lower()
+    assert not [b for b in banned if b in undef]
