@@ -141,6 +141,25 @@ enum { SBIE_MV_FULL = 0, SBIE_MV_DLP_ONLY = 1, SBIE_MV_FULL_ACCURATE = 2 };
 int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y, int mode,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = A x as stokes_dlp_matvec (same modes, kernels and results up to the
+ * rounding order of a different source-chunk count), with no allocation of
+ * any kind.  Its scratch (source records, two scalars, partial sums) is a
+ * fixed 64 MiB device array of the library, one per GPU, held until the
+ * process ends.  The caller passes x and y as for stokes_dlp_matvec.
+ * Limit: 8 Nn + 8 (M + 1) + 8 + (c + ceil(M / 64)) * k * Nn doubles must fit
+ * in 64 MiB with at least c = 1 source chunk, where k = 2 (SBIE_MV_FULL,
+ * SBIE_MV_DLP_ONLY) or 4 (SBIE_MV_FULL_ACCURATE); the source-chunk count is
+ * lowered to fit.  Larger problems return SBIE_INVALID_ARGUMENT before any
+ * launch (without pores: above 0.84 M nodes plain, 0.70 M accurate).  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero: every call writes
+ * what it reads. */
+int stokes_dlp_matvec_noalloc(const sbie_geom *g, const double *x, double *y, int mode,
+                              void *stream);
+
 /* Launch shape of the matvec's pair kernel (chosen by the autotuner):
  * targets_per_thread in {1, 2, 4, 8}; source_chunks >= 1 splits the source
  * loop across that many workgroups per target tile (0 = automatic). */

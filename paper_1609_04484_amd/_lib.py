@@ -98,6 +98,8 @@ EXPORTS = {
     "stokes_bie_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, ctypes.c_int64,
                                            _c_dp, ctypes.c_int64, _c_dp, ctypes.c_int64, _c_dp]),
     "stokes_dlp_matvec": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int, _c_dp]),
+    "stokes_dlp_matvec_noalloc": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int,
+                                                 _c_dp]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -228,6 +230,14 @@ def matvec(dg: DeviceGeometry, x: torch.Tensor, mode: int = 0, out=None, stream=
     y = torch.empty_like(x) if out is None else out
     check(load().stokes_dlp_matvec(ctypes.byref(dg.c), _ptr(x), _ptr(y), mode, _stream(stream)))
     return y
+
+
+def matvec_noalloc(dg: DeviceGeometry, x: torch.Tensor, out: torch.Tensor, mode: int = 0, stream=None):
+    """y = A x through the entry point that allocates nothing (the output
+    must be passed in)."""
+    check(load().stokes_dlp_matvec_noalloc(ctypes.byref(dg.c), _ptr(x), _ptr(out), mode,
+                                           _stream(stream)))
+    return out
 
 
 def set_matvec_shape(targets_per_thread: int, source_chunks: int = 0):

@@ -890,6 +890,70 @@ extern "C" int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y,
   });
 }
 
+// ---------------------------------------------------------------------------
+// Matvec without allocation: the same kernels with their scratch in a fixed
+// device array of the library.  Its name is a host-side stand-in in host
+// code; the device address of each GPU's copy is looked up once per device
+// and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+namespace sbie {
+namespace {
+
+constexpr size_t kNoAllocDoubles = size_t(64) << 17;   // 64 MiB of FP64
+__device__ __align__(256) double g_noalloc_scratch[kNoAllocDoubles];
+
+std::mutex g_noalloc_mu;
+std::vector<double *> g_noalloc_ptr;   // per device, looked up on first use
+
+double *noalloc_scratch() {
+  int dev = 0;
+  SBIE_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if ((int)g_noalloc_ptr.size() <= dev) g_noalloc_ptr.resize(dev + 1, nullptr);
+  if (!g_noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    SBIE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch)));
+    if (!ptr) fail(SBIE_HIP_ERROR, "no device address for the matvec scratch array");
+    g_noalloc_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_noalloc_ptr[dev];
+}
+
+}  // namespace
+}  // namespace sbie
+
+extern "C" int stokes_dlp_matvec_noalloc(const sbie_geom *g, const double *x, double *y, int mode,
+                                         void *stream) {
+  return sbie::guarded([&]() {
+    sbie::validate_geom(g);
+    if (!x || !y) sbie::fail(SBIE_INVALID_ARGUMENT, "null vector");
+    if (mode != SBIE_MV_FULL && mode != SBIE_MV_DLP_ONLY && mode != SBIE_MV_FULL_ACCURATE)
+      sbie::fail(SBIE_INVALID_ARGUMENT, "unknown matvec mode %d", mode);
+    const int64_t n = sbie::n_unknowns(g);
+    if (x < y + n && y < x + n) sbie::fail(SBIE_INVALID_ARGUMENT, "x and y overlap");
+    sbie::MatvecWork w = sbie::plan_matvec(g);
+    // fit the source chunks into the fixed array: records and scalars, then
+    // one partial sum (2 or 4 doubles per node) per pair and pore chunk
+    const int64_t nn = g->n_nodes;
+    const int64_t per = (mode == SBIE_MV_FULL_ACCURATE ? 4 : 2) * nn;
+    const int64_t fixed = 8 * nn + 8 * ((int64_t)g->n_pores + 1) + 8;
+    const int64_t room = (int64_t)sbie::kNoAllocDoubles - fixed;
+    const int64_t max_chunks = room > 0 ? room / per - w.pchunks : 0;
+    if (max_chunks < 1)
+      sbie::fail(SBIE_INVALID_ARGUMENT,
+                 "problem too large for the %zu MiB no-allocation scratch (%lld nodes, %d pores)",
+                 sbie::kNoAllocDoubles * sizeof(double) >> 20, (long long)nn, (int)g->n_pores);
+    if (w.chunks > max_chunks) {
+      int64_t c = max_chunks;
+      if (c >= 16) c &= ~int64_t(7);
+      w.chunks = (int)c;
+    }
+    sbie::bind_matvec_scratch(w, g, sbie::noalloc_scratch());
+    sbie::matvec_run(g, x, y, mode, w, (hipStream_t)stream);
+    return SBIE_OK;
+  });
+}
+
 extern "C" int stokes_dlp_matvec_batched(const sbie_geom *geoms, int32_t count, const double *const *x,
                                          double *const *y, int mode, void *stream) {
   return sbie::guarded([&]() {
