@@ -160,6 +160,28 @@ int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y, int mode,
 int stokes_dlp_matvec_noalloc(const sbie_geom *g, const double *x, double *y, int mode,
                               void *stream);
 
+/* Velocity at points of the fluid from a solved density: the trapezoid rule
+ * of Section 2.2 (equation "stokesSLP_discretized", here for the completed
+ * double-layer representation),
+ *   u(p) = sum_j w_j D(p, x_j, n_j) sigma_j
+ *          + sum_k [ S(p - c_k) lambda_k + r_k R(p - c_k) mu_k ],
+ * with no jump, diagonal limit or wall term (p is off the boundary).
+ *   sigma     device FP64, length n (the unknown vector of gmres_solve).
+ *   px, py    device FP64, np target points.
+ *   ux, uy    device FP64, np outputs.
+ *   uref_x, uref_y, err  optional (all three or none): err[i] = | |u(p_i)|
+ *             - |uref_i| | / |uref_i|, the relative error of the velocity
+ *             magnitude used to assess solutions (Section 4.1.1).
+ * Accuracy: spectral once a point is farther than about sqrt(h) from the
+ * boundary, h the local node spacing (Section 2.2); closer points get the
+ * plain rule (no near-singular correction), and a point on a node gets no
+ * contribution from that node.  Target points must be distinct.
+ * np = 0 returns SBIE_OK.  Errors: SBIE_INVALID_ARGUMENT for null pointers
+ * or np < 0.  Scratch memory comes from the stream-ordered allocator. */
+int stokes_velocity(const sbie_geom *g, const double *sigma, const double *px, const double *py,
+                    int64_t np, double *ux, double *uy, const double *uref_x, const double *uref_y,
+                    double *err, void *stream);
+
 /* Launch shape of the matvec's pair kernel (chosen by the autotuner):
  * targets_per_thread in {1, 2, 4, 8}; source_chunks >= 1 splits the source
  * loop across that many workgroups per target tile (0 = automatic). */

@@ -100,6 +100,8 @@ EXPORTS = {
     "stokes_dlp_matvec": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int, _c_dp]),
     "stokes_dlp_matvec_noalloc": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int,
                                                  _c_dp]),
+    "stokes_velocity": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp, ctypes.c_int64,
+                                       _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -238,6 +240,22 @@ def matvec_noalloc(dg: DeviceGeometry, x: torch.Tensor, out: torch.Tensor, mode:
     check(load().stokes_dlp_matvec_noalloc(ctypes.byref(dg.c), _ptr(x), _ptr(out), mode,
                                            _stream(stream)))
     return out
+
+
+def velocity(dg: DeviceGeometry, sigma: torch.Tensor, px: torch.Tensor, py: torch.Tensor,
+             uref=None, stream=None):
+    """(ux, uy) at the points (px, py); with uref = (ux_ref, uy_ref) also the
+    relative velocity-magnitude error per point: returns (ux, uy, err)."""
+    npts = px.numel()
+    ux = torch.empty_like(px)
+    uy = torch.empty_like(px)
+    err = torch.empty_like(px) if uref is not None else None
+    rx, ry = (uref if uref is not None else (None, None))
+    check(load().stokes_velocity(ctypes.byref(dg.c), _ptr(sigma), _ptr(px), _ptr(py), npts,
+                                 _ptr(ux), _ptr(uy), _ptr(rx) if rx is not None else None,
+                                 _ptr(ry) if ry is not None else None,
+                                 _ptr(err) if err is not None else None, _stream(stream)))
+    return (ux, uy, err) if uref is not None else (ux, uy)
 
 
 def set_matvec_shape(targets_per_thread: int, source_chunks: int = 0):

@@ -243,8 +243,9 @@ constexpr int kTileLanes = 64;
 
 template <int T, bool ACC>
 __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, const double *__restrict__ xs,
-                                               const double *__restrict__ ys, int64_t nn, int64_t chunk,
-                                               double *__restrict__ part, int64_t tile, int64_t ch) {
+                                               const double *__restrict__ ys, int64_t nt, int64_t ns,
+                                               int64_t chunk, double *__restrict__ part, int64_t tile,
+                                               int64_t ch) {
   constexpr int S = (!ACC && T <= 4) ? 2 : 1;
   constexpr int NV = ACC ? 4 : 2;    // values per target in a partial sum
   const int lane = threadIdx.x & 63;
@@ -257,8 +258,8 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
     // padding targets of the last tile sit far away from every node and at
     // distinct places, so at most one target per thread can coincide with a
     // source (the batched reciprocal multiplies the squared distances)
-    xi[t] = i < nn ? xs[i] : xs[nn - 1] + 1.0e3 * (double)(t + 1);
-    yi[t] = i < nn ? ys[i] : ys[nn - 1];
+    xi[t] = i < nt ? xs[i] : xs[nt - 1] + 1.0e3 * (double)(t + 1);
+    yi[t] = i < nt ? ys[i] : ys[nt - 1];
     ax[t] = 0.0;
     ay[t] = 0.0;
     cxa[t] = 0.0;
@@ -268,7 +269,7 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
   // below 2^31), so the loop test is a scalar compare; this wave's quarter
   // of the chunk
   const int c0 = (int)(ch * chunk);
-  const int c1 = (int)(ch * chunk + chunk < nn ? ch * chunk + chunk : nn);
+  const int c1 = (int)(ch * chunk + chunk < ns ? ch * chunk + chunk : ns);
   const int qlen = c1 > c0 ? (c1 - c0 + kWaves - 1) / kWaves : 0;
   const int j0 = __builtin_amdgcn_readfirstlane(c0 + wv * qlen < c1 ? c0 + wv * qlen : c1);
   const int j1 = __builtin_amdgcn_readfirstlane(j0 + qlen < c1 ? j0 + qlen : c1);
@@ -304,16 +305,16 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
         ay[t] += red[o][NV * t + 1][lane];
       }
     }
-  double *px = part + ch * NV * nn;
+  double *px = part + ch * NV * nt;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int64_t i = tile0 + (int64_t)t * kTileLanes;
-    if (i < nn) {
+    if (i < nt) {
       px[i] = ax[t];
-      px[nn + i] = ay[t];
+      px[nt + i] = ay[t];
       if (ACC) {
-        px[2 * nn + i] = cxa[t];
-        px[3 * nn + i] = cya[t];
+        px[2 * nt + i] = cxa[t];
+        px[3 * nt + i] = cya[t];
       }
     }
   }
@@ -326,7 +327,7 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
 template <int T, bool ACC>
 __global__ __launch_bounds__(kBlock) void dlp_pairs(
     const double *__restrict__ src, const double *__restrict__ xs,
-    const double *__restrict__ ys, int64_t nn, int64_t chunk,
+    const double *__restrict__ ys, int64_t nt, int64_t nn, int64_t chunk,
     double *__restrict__ part, int tiles, int xcd) {
   int tile, ch;
   if (xcd) {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
     tile = blockIdx.x % tiles;
     ch = blockIdx.x / tiles;
   }
-  dlp_pairs_body<T, ACC>(src, xs, ys, nn, chunk, part, tile, ch);
+  dlp_pairs_body<T, ACC>(src, xs, ys, nt, nn, chunk, part, tile, ch);
 }
 
 // Stokeslet + rotlet columns: sum over pores of S(x_i - c_k) lambda_k
@@ -636,13 +637,13 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_HIP(hipEventRecord(ev0, s));
   }
   if (acc) {
-    dlp_pairs<1, true><<<grid1, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles1, xcd);
+    dlp_pairs<1, true><<<grid1, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles1, xcd);
   } else {
     switch (w.tpt) {
-      case 1: dlp_pairs<1, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
-      case 2: dlp_pairs<2, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
-      case 4: dlp_pairs<4, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
-      case 8: dlp_pairs<8, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, chunk, w.part, tiles, xcd); break;
+      case 1: dlp_pairs<1, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles, xcd); break;
+      case 2: dlp_pairs<2, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles, xcd); break;
+      case 4: dlp_pairs<4, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles, xcd); break;
+      case 8: dlp_pairs<8, false><<<grid, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles, xcd); break;
       default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
     }
   }
@@ -671,6 +672,71 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
                                g->cx, g->cy, g->radius, x, full, y);
     SBIE_LAUNCH_CHECK();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity at points of the fluid from a solved density: the same source
+// records, pair and completion kernels with the points as targets (no self
+// pair, no jump, no diagonal limit, no wall term), then one epilogue.
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void velocity_epilogue(int64_t np, int nchunks, int npchunks, const double *__restrict__ part,
+                                  double *__restrict__ ux, double *__restrict__ uy,
+                                  const double *__restrict__ rx, const double *__restrict__ ry,
+                                  double *__restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  double vx = 0.0, vy = 0.0, cx = 0.0, cy = 0.0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double *p = part + (int64_t)c * 2 * np;
+    vx += p[i];
+    vy += p[np + i];
+  }
+  for (int c = 0; c < npchunks; ++c) {
+    const double *p = part + (int64_t)(nchunks + c) * 2 * np;
+    cx += p[i];
+    cy += p[np + i];
+  }
+  vx += cx * (0.25 / kPi);
+  vy += cy * (0.25 / kPi);
+  ux[i] = vx;
+  uy[i] = vy;
+  if (err) {
+    // relative error of the velocity magnitude against a reference field
+    const double a = sqrt(vx * vx + vy * vy), b = sqrt(rx[i] * rx[i] + ry[i] * ry[i]);
+    err[i] = fabs(a - b) / b;
+  }
+}
+
+}  // namespace
+
+void velocity_run(const sbie_geom *g, const double *sigma, const double *px, const double *py, int64_t np,
+                  double *ux, double *uy, const double *rx, const double *ry, double *err, hipStream_t s) {
+  const int64_t nn = g->n_nodes;
+  const int m = g->n_pores;
+  const int tpt = 4;
+  const int tiles = (int)ceil_div(np, (int64_t)kTileLanes * tpt);
+  int chunks = g_chunks > 0 ? g_chunks : choose_chunks(nn, tiles, tpt);
+  if ((int64_t)chunks > nn) chunks = (int)nn;
+  const int pchunks = m > 0 ? (int)ceil_div(m, kPoreChunk) : 0;
+  StreamBuf<double> scratch((size_t)8 * nn + (size_t)8 * (m + 1) + (size_t)(chunks + pchunks) * 2 * np, s);
+  double *src = scratch.p, *psrc = src + 8 * nn, *part = psrc + 8 * (m + 1);
+  pack_sources<<<ceil_div(nn > m ? nn : m, 256), 256, 0, s>>>(nn, m, g->x, g->y, g->nx, g->ny, g->w, g->radius,
+                                                             g->cx, g->cy, sigma, src, psrc);
+  SBIE_LAUNCH_CHECK();
+  const int64_t chunk = (nn + chunks - 1) / chunks;
+  const int xcd = (chunks % 8 == 0) ? 1 : 0;
+  dlp_pairs<4, false><<<(unsigned)((int64_t)tiles * chunks), kBlock, 0, s>>>(src, px, py, np, nn, chunk, part,
+                                                                            tiles, xcd);
+  SBIE_LAUNCH_CHECK();
+  if (m > 0) {
+    dim3 pg(ceil_div(np, kBlock), pchunks);
+    completion_pairs<false><<<pg, kBlock, 0, s>>>(psrc, px, py, np, m, part + (size_t)chunks * 2 * np);
+    SBIE_LAUNCH_CHECK();
+  }
+  velocity_epilogue<<<ceil_div(np, 256), 256, 0, s>>>(np, chunks, pchunks, part, ux, uy, rx, ry, err);
+  SBIE_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -719,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs_b(const BMember *__restrict_
   const int b = find_member(st, nb, blockIdx.x);
   const BMember &M = d[b];
   const int64_t u = (int64_t)blockIdx.x - st[b];
-  dlp_pairs_body<T, ACC>(M.src, M.x, M.y, M.nn, M.chunk, M.part, u % M.tiles, u / M.tiles);
+  dlp_pairs_body<T, ACC>(M.src, M.x, M.y, M.nn, M.nn, M.chunk, M.part, u % M.tiles, u / M.tiles);
 }
 
 template <bool ACC>
@@ -977,6 +1043,22 @@ extern "C" int stokes_dlp_matvec_batched(const sbie_geom *geoms, int32_t count, 
     bm.run({}, u, out, mode, (hipStream_t)stream);
     // the batch's scratch is freed on return: wait for its kernels
     SBIE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return SBIE_OK;
+  });
+}
+
+extern "C" int stokes_velocity(const sbie_geom *g, const double *sigma, const double *px, const double *py,
+                               int64_t np, double *ux, double *uy, const double *uref_x,
+                               const double *uref_y, double *err, void *stream) {
+  return sbie::guarded([&]() {
+    sbie::validate_geom(g);
+    if (np < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "np < 0");
+    if (np == 0) return SBIE_OK;
+    if (!sigma || !px || !py || !ux || !uy) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
+    if ((err != nullptr) != (uref_x != nullptr) || (uref_x != nullptr) != (uref_y != nullptr))
+      sbie::fail(SBIE_INVALID_ARGUMENT, "uref_x, uref_y and err go together");
+    if (np > (int64_t)0x7fffffff) sbie::fail(SBIE_INVALID_ARGUMENT, "too many points");
+    sbie::velocity_run(g, sigma, px, py, np, ux, uy, uref_x, uref_y, err, (hipStream_t)stream);
     return SBIE_OK;
   });
 }
