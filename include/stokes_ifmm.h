@@ -281,6 +281,46 @@ int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
                 const gmres_params *p, gmres_result *res, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The single-layer (first-kind) formulation the paper's experiments use
+ * (Section 2.1, equations "stokesSLP" and "stokesBIE"; Section 2.2, the
+ * corrected trapezoid rule).  Unknowns: [sigma_x (Nn) | sigma_y (Nn)], length
+ * 2 Nn, no completion.  Row i:
+ *   (A sigma)_i = sum_{j != i} w_j (1 + gamma_ij) G(x_i - x_j) sigma_j / (4 pi),
+ *   G(r) = -log|r| I + r r^T / |r|^2,
+ * where gamma_ij = gamma_d when j is on the curve of i at periodic index
+ * distance d = 1..6 and 0 otherwise (the six-point-per-side rule for the
+ * logarithmic singularity; the weights are derived from the error expansion
+ * of the punctured trapezoid rule and returned by stokes_slp_weights).  Every
+ * curve needs more than 12 nodes (SBIE_UNSUPPORTED otherwise).  The single
+ * layer of the normal density of any closed curve vanishes on the whole
+ * boundary, so the matrix has M + 1 singular values that go to zero with the
+ * rule's error: the density is determined only up to those directions, the
+ * velocity in the fluid is not affected.
+ * ------------------------------------------------------------------------ */
+/* gamma_1..gamma_6 (host array of 6 doubles). */
+int stokes_slp_weights(double *gamma);
+/* y = A sigma (device FP64, length 2 Nn, no overlap); mode SBIE_MV_FULL or
+ * SBIE_MV_FULL_ACCURATE (compensated sums).  Direct O(Nn^2) evaluation. */
+int stokes_slp_matvec(const sbie_geom *g, const double *x, double *y, int mode, void *stream);
+/* Entries A[rows, cols] (indices in [0, 2 Nn), column-major, ld >= nr). */
+int stokes_slp_assemble(const sbie_geom *g, const int64_t *rows, int64_t nr, const int64_t *cols,
+                        int64_t nc, double *out, int64_t ld, void *stream);
+/* Block-diagonal preconditioner of the single-layer matrix: one exactly
+ * inverted block per curve (Section 4.1.1).  Applied with bd_solve; freed
+ * with bd_destroy. */
+int bd_factor_slp(const sbie_geom *g, sbie_bd **out, void *stream);
+/* FGMRES on the single-layer system, as gmres_solve (f, sigma of length
+ * 2 Nn); pc = 0 or 1 (a handle from bd_factor_slp); pc = 2 returns
+ * SBIE_UNSUPPORTED (the IFMM here is built for the double layer). */
+int gmres_solve_slp(const sbie_geom *g, const double *f, double *sigma,
+                    const gmres_params *p, gmres_result *res, void *stream);
+/* Velocity in the fluid from a single-layer density by the plain trapezoid
+ * rule (equation "stokesSLP_discretized"), arguments as stokes_velocity. */
+int stokes_slp_velocity(const sbie_geom *g, const double *sigma, const double *px, const double *py,
+                        int64_t np, double *ux, double *uy, const double *uref_x, const double *uref_y,
+                        double *err, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batches of independent geometries.
  * ------------------------------------------------------------------------ */
 /* y_b = A_b x_b for every member b (geoms: host array of `count`

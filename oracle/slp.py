@@ -48,18 +48,27 @@ def zeta_prime_neg_even(p: int) -> float:
 
 def kr_log_weights(m: int = 6) -> np.ndarray:
     """Correction weights gamma_1..gamma_m (m even) of the corrected
-    trapezoid rule for a logarithmic singularity at a node."""
+    trapezoid rule for a logarithmic singularity at a node.  The moment
+    system is solved in 40-digit arithmetic (mpmath) and rounded once: its
+    condition number (2.7e5 for m = 6) would cost five digits in FP64."""
+    import mpmath
     assert m % 2 == 0 and m >= 2
     nP = m // 2
-    k = np.arange(1, m + 1, dtype=np.float64)
-    rows, rhs = [], []
-    for p in range(nP):
-        rows.append(2.0 * k ** (2 * p))
-        rhs.append(1.0 if p == 0 else 0.0)
-    for p in range(nP):
-        rows.append(2.0 * k ** (2 * p) * np.log(k))
-        rhs.append(-math.log(2 * math.pi) if p == 0 else 2.0 * zeta_prime_neg_even(p))
-    return np.linalg.solve(np.array(rows), np.array(rhs))
+    with mpmath.workdps(40):
+        rows, rhs = [], []
+        for p in range(nP):
+            rows.append([2 * mpmath.mpf(k) ** (2 * p) for k in range(1, m + 1)])
+            rhs.append(mpmath.mpf(1) if p == 0 else mpmath.mpf(0))
+        for p in range(nP):
+            rows.append([2 * mpmath.mpf(k) ** (2 * p) * mpmath.log(k) for k in range(1, m + 1)])
+            if p == 0:
+                rhs.append(-mpmath.log(2 * mpmath.pi))
+            else:
+                # zeta'(-2p) from the functional equation
+                rhs.append(2 * (-1) ** p * mpmath.factorial(2 * p) * mpmath.zeta(2 * p + 1)
+                           / (2 * (2 * mpmath.pi) ** (2 * p)))
+        sol = mpmath.lu_solve(mpmath.matrix(rows), mpmath.matrix(rhs))
+        return np.array([float(sol[i]) for i in range(m)])
 
 
 def corrected_trapezoid(f_vals: np.ndarray, i: int, h: float, gamma: np.ndarray) -> float:
@@ -121,6 +130,41 @@ def assemble(geom, gamma: np.ndarray | None = None) -> np.ndarray:
     a[nn:, :nn] = c * (rx * ry / rho2)
     a[nn:, nn:] = c * (-lg + ry * ry / rho2)
     return a
+
+
+def rows_of_matrix(geom, rows, gamma: np.ndarray | None = None) -> np.ndarray:
+    """Rows ``rows`` (global indices in [0, 2 Nn)) of the matrix of
+    ``assemble``, computed entry by entry from the same definition."""
+    gamma = kr_log_weights() if gamma is None else gamma
+    m = gamma.shape[0]
+    nn = geom.n_nodes
+    rows = np.asarray(rows, dtype=np.int64)
+    i = np.where(rows < nn, rows, rows - nn)
+    a = np.where(rows < nn, 0, 1)
+    rx = geom.x[i][:, None] - geom.x[None, :]
+    ry = geom.y[i][:, None] - geom.y[None, :]
+    rho2 = rx * rx + ry * ry
+    self_pair = np.arange(nn)[None, :] == i[:, None]
+    rho2 = np.where(self_pair, 1.0, rho2)
+    lg = 0.5 * np.log(rho2)
+    # correction factor of every (row node, column node) pair
+    cid = np.empty(nn, dtype=np.int64)
+    for k in range(geom.n_pores + 1):
+        cid[geom.curve_off[k]:geom.curve_off[k + 1]] = k
+    fac = np.ones((rows.shape[0], nn))
+    for r_, ii in enumerate(i):
+        k = cid[ii]
+        st, en = int(geom.curve_off[k]), int(geom.curve_off[k + 1])
+        n = en - st
+        for d in range(1, m + 1):
+            fac[r_, st + (ii - st + d) % n] += gamma[d - 1]
+            fac[r_, st + (ii - st - d) % n] += gamma[d - 1]
+    c = np.where(self_pair, 0.0, geom.w[None, :] * fac / (4.0 * math.pi))
+    ra = np.where(a[:, None] == 0, rx, ry)
+    out = np.empty((rows.shape[0], 2 * nn))
+    out[:, :nn] = c * (np.where(a[:, None] == 0, -lg, 0.0) + ra * rx / rho2)
+    out[:, nn:] = c * (np.where(a[:, None] == 1, -lg, 0.0) + ra * ry / rho2)
+    return out
 
 
 def velocity(geom, sigma: np.ndarray, px, py) -> tuple:

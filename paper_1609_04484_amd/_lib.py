@@ -102,6 +102,15 @@ EXPORTS = {
                                                  _c_dp]),
     "stokes_velocity": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp, ctypes.c_int64,
                                        _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
+    "stokes_slp_weights": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
+    "stokes_slp_matvec": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, ctypes.c_int, _c_dp]),
+    "stokes_slp_assemble": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, ctypes.c_int64,
+                                           _c_dp, ctypes.c_int64, _c_dp, ctypes.c_int64, _c_dp]),
+    "bd_factor_slp": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(ctypes.c_void_p), _c_dp]),
+    "gmres_solve_slp": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp,
+                                       ctypes.POINTER(GmresParams), ctypes.POINTER(GmresResult), _c_dp]),
+    "stokes_slp_velocity": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp, ctypes.c_int64,
+                                           _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -286,10 +295,15 @@ def assemble(dg: DeviceGeometry, rows, cols, stream=None) -> torch.Tensor:
 
 
 class BlockDiagonal:
-    def __init__(self, dg: DeviceGeometry, stream=None):
+    """Block-diagonal preconditioner of the completed double layer, or of
+    the single layer with single_layer=True."""
+
+    def __init__(self, dg: DeviceGeometry, stream=None, single_layer=False):
         self.dg = dg
+        self.single_layer = single_layer
         h = ctypes.c_void_p()
-        check(load().bd_factor(ctypes.byref(dg.c), ctypes.byref(h), _stream(stream)))
+        fn = load().bd_factor_slp if single_layer else load().bd_factor
+        check(fn(ctypes.byref(dg.c), ctypes.byref(h), _stream(stream)))
         self.h = h
 
     def solve(self, b: torch.Tensor, stream=None) -> torch.Tensor:
@@ -375,6 +389,62 @@ def gmres(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000
                              ctypes.byref(r), _stream(stream)))
     return SolveResult(sigma, r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
                        r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, hist[:r.iters + 1].copy())
+
+
+def slp_weights() -> np.ndarray:
+    """The six correction weights of the single-layer quadrature."""
+    g = (ctypes.c_double * 6)()
+    check(load().stokes_slp_weights(g))
+    return np.array(list(g))
+
+
+def slp_matvec(dg: DeviceGeometry, x: torch.Tensor, accurate=False, out=None, stream=None):
+    """y = A x for the single-layer matrix (2 Nn unknowns)."""
+    y = torch.empty_like(x) if out is None else out
+    check(load().stokes_slp_matvec(ctypes.byref(dg.c), _ptr(x), _ptr(y), 2 if accurate else 0,
+                                   _stream(stream)))
+    return y
+
+
+def slp_assemble(dg: DeviceGeometry, rows, cols, stream=None) -> torch.Tensor:
+    dev = dg.t["x"].device
+    r = torch.as_tensor(np.asarray(rows, dtype=np.int64)).to(dev)
+    c = torch.as_tensor(np.asarray(cols, dtype=np.int64)).to(dev)
+    out = torch.empty((c.numel(), r.numel()), dtype=torch.float64, device=dev)
+    check(load().stokes_slp_assemble(ctypes.byref(dg.c), _ptr(r), r.numel(), _ptr(c), c.numel(),
+                                     _ptr(out), r.numel(), _stream(stream)))
+    return out.t()
+
+
+def gmres_slp(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000,
+              restart=0, x0: torch.Tensor | None = None, stream=None) -> SolveResult:
+    """FGMRES on the single-layer system; pc is None or a single-layer BlockDiagonal."""
+    sigma = torch.zeros_like(f) if x0 is None else x0.clone()
+    hist = np.zeros(max_iter + 2)
+    kind = 0 if pc is None else 1
+    p = GmresParams(tol=tol, max_iter=max_iter, restart=restart, pc=kind,
+                    use_x0=int(x0 is not None), bd=pc.h.value if kind == 1 else None, ifmm=None,
+                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    r = GmresResult()
+    check(load().gmres_solve_slp(ctypes.byref(dg.c), _ptr(f), _ptr(sigma), ctypes.byref(p),
+                                 ctypes.byref(r), _stream(stream)))
+    return SolveResult(sigma, r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
+                       r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, hist[:r.iters + 1].copy())
+
+
+def slp_velocity(dg: DeviceGeometry, sigma: torch.Tensor, px: torch.Tensor, py: torch.Tensor,
+                 uref=None, stream=None):
+    """Velocity from a single-layer density at (px, py); as velocity()."""
+    npts = px.numel()
+    ux = torch.empty_like(px)
+    uy = torch.empty_like(px)
+    err = torch.empty_like(px) if uref is not None else None
+    rx, ry = (uref if uref is not None else (None, None))
+    check(load().stokes_slp_velocity(ctypes.byref(dg.c), _ptr(sigma), _ptr(px), _ptr(py), npts,
+                                     _ptr(ux), _ptr(uy), _ptr(rx) if rx is not None else None,
+                                     _ptr(ry) if ry is not None else None,
+                                     _ptr(err) if err is not None else None, _stream(stream)))
+    return (ux, uy, err) if uref is not None else (ux, uy)
 
 
 class MLP:

@@ -10,11 +10,15 @@
 // updates over the basis V), the norm and the normalisation.  The only
 // per-iteration host crossing is the new Hessenberg column (j + 2 doubles),
 // which the host needs for its Givens rotations and the convergence test.
+// The same driver solves the completed double-layer system and the
+// single-layer (first-kind) system of Section 2.1.
 #include <chrono>
 #include <cmath>
+#include <functional>
 
 #include "common.hpp"
 #include "precond.hpp"
+#include "slp.hpp"
 
 namespace sbie {
 
@@ -135,26 +139,30 @@ struct Timer {
 
 }  // namespace
 
-int gmres_run(const sbie_geom *g, const double *f, double *x,
-              const gmres_params *p, gmres_result *res, hipStream_t s) {
+// The operator of a solve: y = A x in plain FP64 sums (Arnoldi) or with
+// compensated sums (true residuals).
+struct KrylovOp {
+  int64_t n;
+  std::function<void(const double *, double *, bool, hipStream_t)> apply;
+};
+
+int gmres_run_op(const KrylovOp &op, const double *f, double *x,
+                 const gmres_params *p, gmres_result *res, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
-  const int64_t n = n_unknowns(g);
+  const int64_t n = op.n;
   const int max_iter = p->max_iter;
   const int restart = p->restart > 0 && p->restart < max_iter ? p->restart : max_iter;
   const bool use_pc = p->pc != 0;
   const int nch = (int)ceil_div(n, kRows);
   const unsigned nb = ceil_div(n, 256);
 
-  MatvecWork mw = plan_matvec(g);
-  const size_t mv_doubles = matvec_scratch_doubles(mw, g);
   const int64_t basis = (int64_t)restart + 1;
   DevBuf<double> V(basis * n);
   DevBuf<double> Z(use_pc ? (int64_t)restart * n : 0);
-  DevBuf<double> wv(n), r(n), mvs(mv_doubles);
+  DevBuf<double> wv(n), r(n);
   DevBuf<double> part((size_t)nch * (basis + 1) + 16);
   DevBuf<double> hdev(2 * basis + 4);
   DevBuf<int> flag(1);
-  bind_matvec_scratch(mw, g, mvs.p);
   double *hhost = nullptr;
   SBIE_HIP(hipHostMalloc((void **)&hhost, (2 * basis + 4) * sizeof(double), hipHostMallocDefault));
   struct HostFree {
@@ -220,7 +228,7 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
     if (total == 0 && !p->use_x0) {
       SBIE_HIP(hipMemcpyAsync(r.p, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
-      matvec_run(g, x, r.p, SBIE_MV_FULL_ACCURATE, mw, s);
+      op.apply(x, r.p, true, s);
       rsub<<<nb, 256, 0, s>>>(f, n, r.p);
     }
     norm(r.p, hdev.p);
@@ -243,7 +251,7 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
       if (use_pc) apply_pc(vj, zj);
       SBIE_HIP(hipEventRecord(tpc.b, s));
       SBIE_HIP(hipEventRecord(tmv.a, s));
-      matvec_run(g, zj, wv.p, SBIE_MV_FULL, mw, s);
+      op.apply(zj, wv.p, false, s);
       SBIE_HIP(hipEventRecord(tmv.b, s));
       SBIE_HIP(hipEventRecord(tar.a, s));
       const int k = j + 1;
@@ -328,6 +336,25 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
   return status;
 }
 
+int gmres_run(const sbie_geom *g, const double *f, double *x,
+              const gmres_params *p, gmres_result *res, hipStream_t s) {
+  MatvecWork mw = plan_matvec(g);
+  DevBuf<double> mvs(matvec_scratch_doubles(mw, g));
+  bind_matvec_scratch(mw, g, mvs.p);
+  KrylovOp op{n_unknowns(g), [&](const double *in, double *out, bool accurate, hipStream_t st) {
+                matvec_run(g, in, out, accurate ? SBIE_MV_FULL_ACCURATE : SBIE_MV_FULL, mw, st);
+              }};
+  return gmres_run_op(op, f, x, p, res, s);
+}
+
+int gmres_run_slp(const sbie_geom *g, const double *f, double *x,
+                  const gmres_params *p, gmres_result *res, hipStream_t s) {
+  KrylovOp op{2 * g->n_nodes, [&](const double *in, double *out, bool accurate, hipStream_t st) {
+                slp_matvec_run(g, in, out, accurate, st);
+              }};
+  return gmres_run_op(op, f, x, p, res, s);
+}
+
 }  // namespace sbie
 
 extern "C" int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
@@ -342,8 +369,31 @@ extern "C" int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
     if (p->pc < 0 || p->pc > 2) sbie::fail(SBIE_INVALID_ARGUMENT, "unknown preconditioner %d", p->pc);
     const int64_t n = sbie::n_unknowns(g);
     if (f < sigma + n && sigma < f + n) sbie::fail(SBIE_INVALID_ARGUMENT, "f and sigma overlap");
+    if (p->pc == 1 && sbie::bd_size(p->bd) != n)
+      sbie::fail(SBIE_INVALID_ARGUMENT, "the block-diagonal handle belongs to another operator or geometry");
     sbie::validate_geom_device(g, (hipStream_t)stream);
     *res = gmres_result{};
     return sbie::gmres_run(g, f, sigma, p, res, (hipStream_t)stream);
+  });
+}
+
+extern "C" int gmres_solve_slp(const sbie_geom *g, const double *f, double *sigma,
+                               const gmres_params *p, gmres_result *res, void *stream) {
+  return sbie::guarded([&]() {
+    sbie::validate_geom(g);
+    if (!f || !sigma || !p || !res) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
+    if (p->max_iter < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "max_iter < 0");
+    if (!(p->tol > 0.0)) sbie::fail(SBIE_INVALID_ARGUMENT, "tol must be positive");
+    if (p->pc == 2) sbie::fail(SBIE_UNSUPPORTED, "the IFMM preconditioner is built for the double layer only");
+    if (p->pc < 0 || p->pc > 1) sbie::fail(SBIE_INVALID_ARGUMENT, "unknown preconditioner %d", p->pc);
+    if (p->pc == 1 && !p->bd) sbie::fail(SBIE_INVALID_ARGUMENT, "pc=1 needs a block-diagonal handle");
+    const int64_t n = 2 * g->n_nodes;
+    if (f < sigma + n && sigma < f + n) sbie::fail(SBIE_INVALID_ARGUMENT, "f and sigma overlap");
+    if (p->pc == 1 && sbie::bd_size(p->bd) != n)
+      sbie::fail(SBIE_INVALID_ARGUMENT, "the block-diagonal handle does not belong to the single layer");
+    sbie::slp_check_geom(g);
+    sbie::validate_geom_device(g, (hipStream_t)stream);
+    *res = gmres_result{};
+    return sbie::gmres_run_slp(g, f, sigma, p, res, (hipStream_t)stream);
   });
 }

@@ -48,7 +48,10 @@ def test_weights_satisfy_their_moment_conditions():
     assert abs(2 * g.sum() - 1.0) < 1e-12
     assert abs(2 * (g * k ** 2).sum()) < 1e-10
     assert abs(2 * (g * k ** 4).sum()) < 1e-8
-    assert abs(slp.zeta_prime_neg_even(1) - (-0.030448457058393270780)) < 1e-15
+    # zeta'(-2p) from the functional equation against mpmath's own derivative
+    import mpmath
+    for p in (1, 2, 3):
+        assert abs(slp.zeta_prime_neg_even(p) - float(mpmath.zeta(-2 * p, derivative=1))) < 1e-16
 
 
 def test_six_point_rule_order():
@@ -125,3 +128,13 @@ def test_exact_stokeslet_solution_converges():
     assert errs[0] > errs[1] > errs[2]
     assert errs[1] / errs[2] > 16
     assert errs[2] < 1e-6
+
+
+def test_rows_agree_with_assembled_matrix():
+    """The row-by-row evaluation used for sampled checks at large sizes
+    equals the assembled matrix (pores and wall, corrections included)."""
+    cx, cy, rr = place_pores(np.random.default_rng(3), 5, 4.0, 0.05, 0.1, 0.05, 0.1)
+    g = build_geometry(4.0, 256, cx, cy, rr, 32)
+    a = slp.assemble(g)
+    rows = np.array([0, 5, 31, 32, 100, g.n_nodes - 1, g.n_nodes, g.n_nodes + 7, 2 * g.n_nodes - 1])
+    assert np.array_equal(slp.rows_of_matrix(g, rows), a[rows])
