@@ -31,7 +31,7 @@ PAIR_FLOPS = 19                # algorithmic flops per node pair of the matvec
 # read off a plain 1 GiB device copy; profiles/dlp_pairs_pipe1000_hbm_counters.md).
 # Valid only for the kernel source they were taken with: reported as null
 # once matvec.hip changes.
-PAIR_TRAFFIC = {"matvec_sha256": "62d6dcdc01836aa85a248db2865465de7424b98a701c4a0a6720d8f7626db3f4", "bytes_per_launch": 148246835,
+PAIR_TRAFFIC = {"matvec_sha256": "12684c5fadcb042194e474f27ecf6d39a9197d8befabfdcb11ac51cf85fc0cae", "bytes_per_launch": 43654144,
                 "workload": "pipe1000"}
 
 

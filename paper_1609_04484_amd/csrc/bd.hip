@@ -2,6 +2,8 @@
 // of every pore (its nodes plus its three constraint unknowns) and of the
 // wall, each assembled on the device and inverted exactly.  Applying it is
 // one batched block GEMV for the pores and one split-K GEMV for the wall.
+#include <algorithm>
+
 #include "assemble.hpp"
 #include "batched.hpp"
 #include "dense.hpp"
@@ -22,6 +24,48 @@ struct sbie_bd {
 };
 
 namespace sbie {
+
+namespace {
+
+// In-place inverse of the wall block (n x n, column-major, ld n) by blocked
+// Gauss-Jordan elimination over nb x nb pivot tiles: each tile is inverted
+// with partial pivoting inside it (one workgroup), the rank-nb updates run
+// on the FP64 matrix-core GEMM tiles.  There is no pivoting across tiles;
+// the second-kind wall block is well conditioned and diagonally dominant in
+// its tiles (the -1/2 jump).  A singular tile raises SBIE_BREAKDOWN.
+void wall_inverse_tiles(double *M, int n, int nb, hipStream_t s) {
+  const int npan = (n + nb - 1) / nb;
+  StreamBuf<double> P((size_t)nb * nb, s), Z((size_t)nb * nb, s), C((size_t)n * nb, s), R((size_t)nb * n, s);
+  StreamBuf<int32_t> info((size_t)npan, s);
+  fill_value<double>(Z.p, (size_t)nb * nb, 0.0, s);
+  fill_value<int>(reinterpret_cast<int *>(info.p), (size_t)npan, 0, s);
+  Stager st((size_t)4 << 20);
+  for (int it = 0; it < npan; ++it) {
+    const int p0 = it * nb, pb = std::min(nb, n - p0);
+    double *Mpp = M + p0 + (size_t)p0 * n;
+    copy_batched<double>({{Mpp, n, P.p, pb, pb, pb, 0, 0, 1.0}}, st, s);
+    inverse_batched<double>({P.p}, {pb}, info.p + it, st, s);
+    // C = M[:, p] with its pivot rows zeroed
+    copy_batched<double>({{M + (size_t)p0 * n, n, C.p, n, n, pb, 0, 0, 1.0}}, st, s);
+    copy_batched<double>({{Z.p, nb, C.p + p0, n, pb, pb, 0, 0, 1.0}}, st, s);
+    // R = P M[p, :] with its pivot columns zeroed
+    gemm_batched<double>({{pb, n, pb, 0, 0, P.p, pb, M + p0, n, R.p, pb, 1.0, 0.0}}, st, s);
+    copy_batched<double>({{Z.p, nb, R.p + (size_t)p0 * pb, pb, pb, pb, 0, 0, 1.0}}, st, s);
+    // every row outside p: M -= C R (pivot rows and columns untouched)
+    gemm_batched<double>({{n, n, pb, 0, 0, C.p, n, R.p, pb, M, n, -1.0, 1.0}}, st, s);
+    // pivot rows = R, pivot columns = -C P, pivot tile = P
+    copy_batched<double>({{R.p, pb, M + p0, n, pb, n, 0, 0, 1.0}}, st, s);
+    gemm_batched<double>({{n, pb, pb, 0, 0, C.p, n, P.p, pb, M + (size_t)p0 * n, n, -1.0, 0.0}}, st, s);
+    copy_batched<double>({{P.p, pb, Mpp, n, pb, pb, 0, 0, 1.0}}, st, s);
+  }
+  std::vector<int32_t> h(npan);
+  SBIE_HIP(hipMemcpyAsync(h.data(), info.p, npan * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SBIE_HIP(hipStreamSynchronize(s));
+  for (int it = 0; it < npan; ++it)
+    if (h[it] != 0) fail(SBIE_BREAKDOWN, "wall block: singular pivot tile at row %d", it * nb);
+}
+
+}  // namespace
 
 void bd_build(const sbie_geom *g, sbie_bd *bd, hipStream_t s) {
   const int64_t nn = g->n_nodes;
@@ -80,18 +124,7 @@ void bd_build(const sbie_geom *g, sbie_bd *bd, hipStream_t s) {
     assemble_block(v, bd->widx.p, bd->nwall, bd->widx.p, bd->nwall, bd->wmat.p, bd->nwall, s);
     if (bd->nwall > 8192)
       fail(SBIE_UNSUPPORTED, "wall block of order %lld exceeds 8192", (long long)bd->nwall);
-    // blocked Gauss-Jordan with partial pivoting by columns; its rank-32
-    // updates run on the FP64 matrix-core GEMM tiles (the descriptors of
-    // all panel steps are staged in one transfer)
-    {
-      Stager st((size_t)48 << 20);
-      DevBuf<int32_t> winfo(1);
-      inverse_batched_blocked<double>({bd->wmat.p}, {(int)bd->nwall}, winfo.p, st, s);
-      int32_t hw = 0;
-      SBIE_HIP(hipMemcpyAsync(&hw, winfo.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      SBIE_HIP(hipStreamSynchronize(s));
-      if (hw != 0) fail(SBIE_BREAKDOWN, "wall block is singular (pivot %d)", (int)hw);
-    }
+    wall_inverse_tiles(bd->wmat.p, (int)bd->nwall, 128, s);
     bd->wch = (int)((bd->nwall + 255) / 256);
     if (bd->wch > 64) bd->wch = 64;
     bd->wpart.alloc((size_t)bd->wch * bd->nwall);

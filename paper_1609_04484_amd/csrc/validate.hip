@@ -2,16 +2,19 @@
 // (Section 2: a closed outer wall enclosing disjoint circular pores, each
 // curve discretised by distinct trapezoid nodes, Section 2.2).
 //
-// Three small kernels set bits of one status word:
+// Four small kernels set bits of one status word:
 //   node_checks   every node: finite data, positive weight, unit normal;
-//                 pore nodes on their circle; no node repeated later on its
-//                 own curve (distinct curves cannot share a node once the
-//                 pores are disjoint circles strictly inside the wall)
+//                 pore nodes on their circle
+//   dup_checks    no node repeated on its own curve (distinct curves cannot
+//                 share a node once the pores are disjoint circles strictly
+//                 inside the wall); node i against one 256-node slice of the
+//                 later nodes of its curve per thread
 //   pore_pairs    every pair of pores: the discs do not touch
 //   pore_in_wall  every pore: its centre inside the wall polygon (crossing
 //                 count of a ray in +x) and every wall node outside its disc
 // The word is read back once; a non-zero word becomes SBIE_INVALID_GEOMETRY
 // with the reasons in the message.
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -60,13 +63,23 @@ __global__ void node_checks(int64_t nn, int m, const int64_t *__restrict__ off,
     const double dx = xi - cx[k], dy = yi - cy[k], r = rad[k];
     if (!(fabs(dx * dx + dy * dy - r * r) <= 1e-8 * r * r)) f |= kOffCircle;
   }
-  const int64_t end = off[k + 1];
-  for (int64_t j = i + 1; j < end; ++j)
-    if (x[j] == xi && y[j] == yi) {
-      f |= kDuplicate;
-      break;
-    }
   if (f) atomicOr(flags, f);
+}
+
+constexpr int kDupSlice = 256;
+
+__global__ void dup_checks(int64_t nn, int m, const int64_t *__restrict__ off, const double *__restrict__ x,
+                           const double *__restrict__ y, unsigned *flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int k = curve_of(off, m + 1, i);
+  const int64_t lo = off[k] + (int64_t)blockIdx.y * kDupSlice, hi = min(off[k + 1], lo + kDupSlice);
+  const double xi = x[i], yi = y[i];
+  for (int64_t j = max(i + 1, lo); j < hi; ++j)
+    if (x[j] == xi && y[j] == yi) {
+      atomicOr(flags, kDuplicate);
+      return;
+    }
 }
 
 __global__ void pore_pairs(int m, const double *__restrict__ cx, const double *__restrict__ cy,
@@ -128,6 +141,11 @@ void validate_geom_device(const sbie_geom *g, hipStream_t s) {
   SBIE_HIP(hipMemsetAsync(flags.p, 0, sizeof(unsigned), s));
   node_checks<<<ceil_div(nn, 256), 256, 0, s>>>(nn, m, g->curve_off_dev, g->x, g->y, g->nx, g->ny, g->w,
                                                 g->kappa, g->cx, g->cy, g->radius, flags.p);
+  SBIE_LAUNCH_CHECK();
+  int64_t longest = 0;
+  for (int k = 0; k <= m; ++k) longest = std::max<int64_t>(longest, g->curve_off[k + 1] - g->curve_off[k]);
+  dup_checks<<<dim3(ceil_div(nn, 256), ceil_div(longest, kDupSlice)), 256, 0, s>>>(nn, m, g->curve_off_dev, g->x,
+                                                                                 g->y, flags.p);
   SBIE_LAUNCH_CHECK();
   if (m > 0) {
     pore_pairs<<<ceil_div((int64_t)m * m, 256), 256, 0, s>>>(m, g->cx, g->cy, g->radius, flags.p);

@@ -1,9 +1,10 @@
 #!/usr/bin/env python3
-"""Write the stored reference solutions sigma* = A^{-1} F of the two large
+"""Write the stored reference solutions sigma* = A^{-1} F of the large
 workloads, using the CPU oracle only (``oracle/`` and the seeded inputs).
 
     python tests/golden/make_sigma.py pipe200    # n = 59,992: dense LU
     python tests/golden/make_sigma.py pipe1000   # n = 139,192: oracle FGMRES
+    python tests/golden/make_sigma.py batch      # batch members with n <= 20,000: dense LU
 
 * pipe200 (seed 100, Poiseuille data): the completed double-layer matrix is
   assembled densely by the NumPy oracle (28.8 GB), factorised by LAPACK
@@ -17,6 +18,9 @@ workloads, using the CPU oracle only (``oracle/`` and the seeded inputs).
   evaluated in 80-bit arithmetic, and the run stops at a true relative
   residual of 1e-13 (a restart from the current iterate is one step of
   iterative refinement).
+
+* batch members (seeds 1000-1063 of the batched workload, Poiseuille data):
+  those with at most 20,000 unknowns, by the dense LU of pipe200.
 
 Each run writes ``sigma_<workload>_s<seed>.npy`` (FP64, no pickle) and a
 JSON record with the method, the final residual (80-bit evaluation), the
@@ -37,7 +41,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import capply, dlp, solve  # noqa: E402
-from stokes_inputs import make_geometry, poiseuille_rhs  # noqa: E402
+from stokes_inputs import batch_member, make_geometry, poiseuille_rhs  # noqa: E402
 
 SEEDS = {"pipe200": 100, "pipe1000": 300}
 
@@ -114,14 +118,28 @@ def fgmres_bd(g, f, tol=1e-13, max_iter=3000):
                        rel_res_true=float(res.rel_res_true), tol=tol)
 
 
+BATCH_SEEDS = range(1000, 1064)      # the 64 members of the batched workload
+BATCH_MAX_N = 20000                   # members solved by dense LU here
+
+
 def main():
     work = sys.argv[1] if len(sys.argv) > 1 else "pipe200"
+    if work == "batch":
+        # every member of the batched workload small enough for a dense LU
+        for sd in BATCH_SEEDS:
+            if batch_member(sd).n_unknowns <= BATCH_MAX_N:
+                solve_one("member", sd)
+        return
     seed = int(sys.argv[2]) if len(sys.argv) > 2 else SEEDS[work]
-    g = make_geometry(work, seed)
+    solve_one(work, seed)
+
+
+def solve_one(work, seed):
+    g = batch_member(seed) if work == "member" else make_geometry(work, seed)
     f = poiseuille_rhs(g)
     log(f"{work} seed {seed}: Nn={g.n_nodes} n={g.n_unknowns}")
     t0 = time.perf_counter()
-    x, meta = dense_lu(g, f) if work == "pipe200" else fgmres_bd(g, f)
+    x, meta = dense_lu(g, f) if work in ("pipe200", "member") else fgmres_bd(g, f)
     wall = time.perf_counter() - t0
     r = true_residual(g, f, x)
     meta.update(workload=work, seed=seed, n=int(g.n_unknowns), rhs="poiseuille k=4",
