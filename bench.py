@@ -133,6 +133,82 @@ def cpu_baseline(g, f, bd_iters):
             "iterations": bd_iters}
 
 
+def fmm_comparison(lib, dg, n, orders=(8, 10, 12, 14)):
+    """The fast-multipole product against the direct one on the bench pipe:
+    plan time (host), time per product (HIP events, 10 products) and the
+    largest difference relative to the largest entry of the direct result."""
+    import numpy as np
+    import torch
+    x = dg.vector(np.random.default_rng(11).standard_normal(n))
+    direct = lib.matvec(dg, x)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_direct = timed(lambda: lib.matvec(dg, x, out=direct))
+    out = {"direct_ms": t_direct, "orders": {}}
+    y = torch.empty_like(x)
+    for p in orders:
+        t0 = time.perf_counter()
+        fm = lib.FMM(dg, cheb_n=p)
+        t_plan = time.perf_counter() - t0
+        ms = timed(lambda: fm.matvec(x, out=y))
+        err = float((y - direct).abs().max() / direct.abs().max())
+        out["orders"][p] = {"ms": ms, "plan_s": t_plan, "rel_diff_vs_direct": err, **fm.stats()}
+        fm.close()
+    return out
+
+
+def complexity_scan(lib, args):
+    """IFMM factor time and algorithmic flops (products 2mnk, inverses 2n^3)
+    against the unknown count for pipes of the bench family at the same pore
+    density (20 pores per unit length, wall spacing 0.025), fixed eps and
+    Chebyshev order; the log-log slope of time against n."""
+    import numpy as np
+    import torch
+    from stokes_inputs import make_geometry
+    rows = []
+    for m in (125, 250, 500, 1000, 2000):
+        length = m / 20.0
+        n_ext = 64 * int(math.ceil((2 * length + 2) / 0.025 / 64))
+        g = make_geometry("pipe1000", 300, length=length, n_pores=m, n_ext=n_ext)
+        dg = lib.DeviceGeometry(g)
+        times, st = [], None
+        try:
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pc = lib.IFMM(dg, eps=args.eps, cheb_n=args.cheb_n, precision=0)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                st = pc.stats()
+                pc.close()
+        except lib.SbieError as e:
+            # e.g. a leaf box smaller than a pore diameter on the longest pipe
+            log(f"[bench] scan {m} pores n={g.n_unknowns}: {e}")
+            continue
+        t = float(np.median(times[1:]))
+        rows.append(dict(pores=m, n=g.n_unknowns, t_factor_s=t, levels=st["levels"],
+                         max_rank=st["max_rank"], factor_bytes=st["factor_bytes"],
+                         gemm_flops=st["gemm_flops"], inverse_flops=st["inverse_flops"],
+                         alg_tflops=(st["gemm_flops"] + st["inverse_flops"]) / t / 1e12))
+        log(f"[bench] scan {m} pores n={g.n_unknowns}: {t:.4f}s")
+    ln = np.log([r["n"] for r in rows])
+    slope_t = float(np.polyfit(ln, np.log([r["t_factor_s"] for r in rows]), 1)[0])
+    slope_f = float(np.polyfit(ln, np.log([r["gemm_flops"] + r["inverse_flops"] for r in rows]), 1)[0])
+    slope_b = float(np.polyfit(ln, np.log([r["factor_bytes"] for r in rows]), 1)[0])
+    return dict(eps=args.eps, cheb_n=args.cheb_n, rows=rows, slope_time=slope_t,
+                slope_flops=slope_f, slope_bytes=slope_b)
+
+
 def recorded_oracle_solve(workload, seed):
     """The whole oracle solve that wrote the stored reference solution of
     this pipe (tests/golden/make_sigma.py), as recorded when it ran."""
@@ -179,10 +255,15 @@ def main():
     ap.add_argument("--chunks", type=int, default=0,
                     help="pair-kernel source chunks (0 = the library's occupancy-based choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fmm", action="store_true",
+                    help="skip the fast-multipole product comparison")
     ap.add_argument("--stored-gemv", default="",
                     help="also time y = A x with A assembled and stored densely (HBM-bound "
                          "comparison) on this workload, e.g. pipe200")
-    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--complexity-scan", action="store_true",
+                    help="also factor pipes of the bench family with 125, 250, 500, 1000 and "
+                         "2000 pores (same density) and report IFMM factor time and "
+                         "algorithmic flops against n (Section 3.3's linear complexity)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -367,6 +448,16 @@ def main():
         cpu["full_oracle_solve_recorded"] = recorded_oracle_solve(args.workload, seeds[0])
         log(f"[bench] cpu baseline: {cpu}")
 
+    fmm = None
+    if not args.no_fmm:
+        fmm = fmm_comparison(lib, dg, n)
+        log(f"[bench] fast-multipole products: {fmm}")
+
+    scan = None
+    if args.complexity_scan:
+        scan = complexity_scan(lib, args)
+        log(f"[bench] complexity scan: {scan}")
+
     stored = None
     if args.stored_gemv:
         # the matrix-free product against a stored dense matrix (assembled by
@@ -434,6 +525,8 @@ def main():
         "matvec_effective_GBps": matvec_gbs,
         "oracle_sampled_row_residual": row_res,
         "stored_matrix_comparison": stored,
+        "complexity_scan": scan,
+        "fmm_matvec": fmm,
     }
     print(json.dumps(line), flush=True)
 

@@ -218,6 +218,19 @@ int bd_destroy(sbie_bd *bd);
  *                2 = FP64 factor stored a second time in FP32: ifmm_solve
  *                reads only that copy, widening each entry to FP64 (vectors
  *                and arithmetic stay FP64), so it moves half the bytes.
+ *   compress     inputs of the two Gaussian-sketch products of the fill-in
+ *                recompression (far fill-in blocks times a Gaussian matrix,
+ *                and wide candidate sets times a Gaussian matrix, whose
+ *                results only have to span the fill-ins' column spaces):
+ *                0 = the factor's precision; 1 = rounded to FP16, 2 = rounded
+ *                to BF16, both multiplied on the matrix cores with FP32
+ *                accumulation.  The rounding perturbs each (norm-scaled)
+ *                block by about the format's unit roundoff (FP16 4.9e-4,
+ *                BF16 3.9e-3), which bounds the compression error from below:
+ *                suited to eps >= 1e-3 (FP16) and eps >= 1e-2 (BF16).
+ *                Every other product of the factorisation stays in the
+ *                factor's precision.
+ *   reserved     must be 0.
  * ifmm_solve computes x ~ A^{-1} b (device FP64, length n).
  * Errors: SBIE_UNSUPPORTED if a pore is larger than a leaf box allows;
  * SBIE_BREAKDOWN on a singular pivot. */
@@ -227,6 +240,8 @@ typedef struct {
   int32_t leaf_target;
   int32_t max_depth;
   int32_t precision;
+  int32_t compress;
+  int32_t reserved;
 } ifmm_params;
 typedef struct ifmm_handle ifmm_handle;
 int ifmm_factor(const sbie_geom *g, const ifmm_params *p, ifmm_handle **out,
@@ -234,7 +249,11 @@ int ifmm_factor(const sbie_geom *g, const ifmm_params *p, ifmm_handle **out,
 int ifmm_solve(const ifmm_handle *h, const double *b, double *x, void *stream);
 int ifmm_destroy(ifmm_handle *h);
 /* Statistics of a factorisation (host): levels, leaves, max rank, factor
- * bytes and factor time in seconds. */
+ * bytes and factor time in seconds; the algorithmic flops of its dense
+ * products (2 m n k per product) and inverses (2 n^3 per Gauss-Jordan
+ * inverse), summed from the operations it issued (the sketched pivoted
+ * Gram-Schmidt, copies and norms are not counted); gemm_low_flops is the
+ * part of gemm_flops run with FP16 or BF16 inputs. */
 typedef struct {
   int32_t levels;
   int32_t leaves;
@@ -242,6 +261,9 @@ typedef struct {
   int32_t reserved;
   int64_t factor_bytes;
   double factor_seconds;
+  double gemm_flops;
+  double inverse_flops;
+  double gemm_low_flops;
 } ifmm_stats;
 int ifmm_get_stats(const ifmm_handle *h, ifmm_stats *s);
 
@@ -256,7 +278,12 @@ int ifmm_get_stats(const ifmm_handle *h, ifmm_stats *s);
  *            must be set).
  *   res_hist (host, optional) max_iter + 2 doubles: relative residual per
  *            iteration.
+ *   fmm      (optional) a fast-multipole plan of the same geometry: the
+ *            Arnoldi products then use it (stokes_dlp_matvec_fmm), while
+ *            every true residual keeps the direct compensated product, so
+ *            the stopping test is the same as without it.  NULL = direct.
  * Returns SBIE_OK, SBIE_NOT_CONVERGED (sigma = best iterate) or an error. */
+typedef struct sbie_fmm sbie_fmm;
 typedef struct {
   double tol;
   int32_t max_iter;
@@ -266,6 +293,7 @@ typedef struct {
   const sbie_bd *bd;
   const ifmm_handle *ifmm;
   double *res_hist;
+  const sbie_fmm *fmm;
 } gmres_params;
 typedef struct {
   int32_t iters;
@@ -279,6 +307,57 @@ typedef struct {
 } gmres_result;
 int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
                 const gmres_params *p, gmres_result *res, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Fast multipole evaluation of the double-layer pair sum (Section 2.2: the
+ * matrix-vector products of GMRES can be computed by a fast multipole
+ * method in O(N) work).  Black-box FMM with Chebyshev interpolation (the
+ * far-field approximation of Section 3.1's H^2 operators): a uniform
+ * quadtree on the bounding square of the nodes (non-empty boxes only),
+ * cheb_n x cheb_n tensor Chebyshev grids per box carrying the multipole
+ * tensors of the sources and the local velocities, interaction lists of
+ * the well-separated boxes (children of the parent's neighbours that do
+ * not touch the box) and direct sums between touching leaves.  Only the
+ * pair sum sum_{j != i} w_j (1/pi) (r.n_j) r r^T / rho^4 sigma_j changes;
+ * every other term of the operator is evaluated as in stokes_dlp_matvec.
+ * The error is that of the interpolation: it falls geometrically with
+ * cheb_n, about a factor 4.5 per order (relative to the largest entry of
+ * the product on the pipes of the tests: 2.6e-5 at 6, 1.3e-7 at 10, 3e-10
+ * at 14, 1.2e-11 at 16); a quadtree of depth 0 or 1 has no far field and
+ * gives the direct sum.
+ *   cheb_n       Chebyshev nodes per direction: 4, 6, ..., 16.
+ *   leaf_target  with max_depth = 0: the shallowest depth whose non-empty
+ *                leaves hold at most this many nodes on average (0 = 64).
+ *   max_depth    the quadtree depth (0 = from leaf_target; at most 20).
+ *   reserved     must be 0.
+ * fmm_plan builds the tree and its lists on the host from the node
+ * positions (read once from the device; synchronises) and keeps a copy of
+ * the geometry descriptor: the geometry's arrays must outlive the plan, and
+ * the plan must be rebuilt when the nodes move.  Calls that use one plan
+ * must be ordered (one stream): they share its device buffers. */
+typedef struct {
+  int32_t cheb_n;
+  int32_t leaf_target;
+  int32_t max_depth;
+  int32_t reserved;
+} fmm_params;
+int fmm_plan(const sbie_geom *g, const fmm_params *p, sbie_fmm **out, void *stream);
+/* y = A x as stokes_dlp_matvec with the pair sum from the plan; modes
+ * SBIE_MV_FULL and SBIE_MV_DLP_ONLY (SBIE_MV_FULL_ACCURATE: SBIE_UNSUPPORTED). */
+int stokes_dlp_matvec_fmm(const sbie_fmm *plan, const double *x, double *y, int mode,
+                          void *stream);
+/* Shape of a plan (host): depth, non-empty leaves, boxes over all levels,
+ * box pairs in the interaction lists and node pairs summed directly. */
+typedef struct {
+  int32_t depth;
+  int32_t leaves;
+  int32_t boxes;
+  int32_t reserved;
+  int64_t m2l_box_pairs;
+  int64_t near_node_pairs;
+} fmm_stats;
+int fmm_get_stats(const sbie_fmm *plan, fmm_stats *s);
+int fmm_destroy(sbie_fmm *plan);
 
 /* ------------------------------------------------------------------------
  * The single-layer (first-kind) formulation the paper's experiments use

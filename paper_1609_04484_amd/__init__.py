@@ -1,7 +1,7 @@
 """MI355X-native solver for the completed double-layer Stokes system of a
 pipe filled with circular pores: HIP kernels behind a C ABI
 (``include/stokes_ifmm.h``) and this thin Python binding."""
-from ._lib import (MLP, BlockDiagonal, DeviceGeometry, IFMM, SbieError, SolveResult,  # noqa: F401
+from ._lib import (FMM, MLP, BlockDiagonal, DeviceGeometry, IFMM, SbieError, SolveResult,  # noqa: F401
                    assemble, gmres, gmres_batched, ifmm_factor_batched, kernel_time,
                    kernel_timing, load, matvec, matvec_batched, matvec_noalloc, set_matvec_shape,
                    validate, velocity, slp_weights, slp_matvec, slp_assemble, gmres_slp,

@@ -43,7 +43,16 @@ class IfmmParams(ctypes.Structure):
         ("leaf_target", ctypes.c_int32),
         ("max_depth", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("compress", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
+
+
+COMPRESS = {"working": 0, "fp16": 1, "bf16": 2}
+
+
+def _compress(c):
+    return COMPRESS[c] if isinstance(c, str) else int(c)
 
 
 class IfmmStats(ctypes.Structure):
@@ -54,6 +63,9 @@ class IfmmStats(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("factor_bytes", ctypes.c_int64),
         ("factor_seconds", ctypes.c_double),
+        ("gemm_flops", ctypes.c_double),
+        ("inverse_flops", ctypes.c_double),
+        ("gemm_low_flops", ctypes.c_double),
     ]
 
 
@@ -67,6 +79,27 @@ class GmresParams(ctypes.Structure):
         ("bd", ctypes.c_void_p),
         ("ifmm", ctypes.c_void_p),
         ("res_hist", ctypes.POINTER(ctypes.c_double)),
+        ("fmm", ctypes.c_void_p),
+    ]
+
+
+class FmmParams(ctypes.Structure):
+    _fields_ = [
+        ("cheb_n", ctypes.c_int32),
+        ("leaf_target", ctypes.c_int32),
+        ("max_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class FmmStats(ctypes.Structure):
+    _fields_ = [
+        ("depth", ctypes.c_int32),
+        ("leaves", ctypes.c_int32),
+        ("boxes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("m2l_box_pairs", ctypes.c_int64),
+        ("near_node_pairs", ctypes.c_int64),
     ]
 
 
@@ -111,6 +144,11 @@ EXPORTS = {
                                        ctypes.POINTER(GmresParams), ctypes.POINTER(GmresResult), _c_dp]),
     "stokes_slp_velocity": (ctypes.c_int, [ctypes.POINTER(SbieGeom), _c_dp, _c_dp, _c_dp, ctypes.c_int64,
                                            _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]),
+    "fmm_plan": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(FmmParams),
+                                ctypes.POINTER(ctypes.c_void_p), _c_dp]),
+    "stokes_dlp_matvec_fmm": (ctypes.c_int, [ctypes.c_void_p, _c_dp, _c_dp, ctypes.c_int, _c_dp]),
+    "fmm_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(FmmStats)]),
+    "fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -325,13 +363,15 @@ class BlockDiagonal:
 
 class IFMM:
     def __init__(self, dg: DeviceGeometry, eps=1e-6, cheb_n=10, leaf_target=64,
-                 max_depth=0, precision=0, stream=None, handle=None):
+                 max_depth=0, precision=0, compress=0, stream=None, handle=None):
+        """compress: inputs of the recompression's Gaussian sketches, 0 or
+        "working" (the factor's precision), 1 or "fp16", 2 or "bf16"."""
         self.dg = dg
         if handle is not None:          # adopt a handle made by ifmm_factor_batched
             self.h = handle
             return
         p = IfmmParams(eps=eps, cheb_n=cheb_n, leaf_target=leaf_target,
-                       max_depth=max_depth, precision=precision)
+                       max_depth=max_depth, precision=precision, compress=_compress(compress))
         h = ctypes.c_void_p()
         check(load().ifmm_factor(ctypes.byref(dg.c), ctypes.byref(p), ctypes.byref(h),
                                  _stream(stream)))
@@ -374,8 +414,9 @@ class SolveResult:
 
 
 def gmres(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000,
-          restart=0, x0: torch.Tensor | None = None, stream=None) -> SolveResult:
-    """FGMRES solve of A sigma = f; pc is None, a BlockDiagonal or an IFMM."""
+          restart=0, x0: torch.Tensor | None = None, stream=None, fmm=None) -> SolveResult:
+    """FGMRES solve of A sigma = f; pc is None, a BlockDiagonal or an IFMM;
+    fmm (an FMM plan of dg) evaluates the Arnoldi products."""
     sigma = torch.zeros_like(f) if x0 is None else x0.clone()
     hist = np.zeros(max_iter + 2)
     kind = 0 if pc is None else (1 if isinstance(pc, BlockDiagonal) else 2)
@@ -383,12 +424,46 @@ def gmres(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000
                     use_x0=int(x0 is not None),
                     bd=pc.h.value if kind == 1 else None,
                     ifmm=pc.h.value if kind == 2 else None,
-                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    fmm=fmm.h.value if fmm is not None else None)
     r = GmresResult()
     check(load().gmres_solve(ctypes.byref(dg.c), _ptr(f), _ptr(sigma), ctypes.byref(p),
                              ctypes.byref(r), _stream(stream)))
     return SolveResult(sigma, r.iters, r.status, r.rel_res_true, r.rel_res_pc, r.t_precond_s,
                        r.t_matvec_s, r.t_arnoldi_s, r.t_total_s, hist[:r.iters + 1].copy())
+
+
+class FMM:
+    """Fast-multipole plan of a geometry (Chebyshev interpolation on a
+    uniform quadtree) for the double-layer pair sum."""
+
+    def __init__(self, dg: DeviceGeometry, cheb_n=12, leaf_target=64, max_depth=0, stream=None):
+        self.dg = dg
+        p = FmmParams(cheb_n=cheb_n, leaf_target=leaf_target, max_depth=max_depth)
+        h = ctypes.c_void_p()
+        check(load().fmm_plan(ctypes.byref(dg.c), ctypes.byref(p), ctypes.byref(h), _stream(stream)))
+        self.h = h
+
+    def matvec(self, x: torch.Tensor, mode: int = 0, out=None, stream=None) -> torch.Tensor:
+        y = torch.empty_like(x) if out is None else out
+        check(load().stokes_dlp_matvec_fmm(self.h, _ptr(x), _ptr(y), mode, _stream(stream)))
+        return y
+
+    def stats(self) -> dict:
+        s = FmmStats()
+        check(load().fmm_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in FmmStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.h:
+            load().fmm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def slp_weights() -> np.ndarray:
@@ -417,14 +492,16 @@ def slp_assemble(dg: DeviceGeometry, rows, cols, stream=None) -> torch.Tensor:
 
 
 def gmres_slp(dg: DeviceGeometry, f: torch.Tensor, pc=None, tol=1e-10, max_iter=2000,
-              restart=0, x0: torch.Tensor | None = None, stream=None) -> SolveResult:
-    """FGMRES on the single-layer system; pc is None or a single-layer BlockDiagonal."""
+              restart=0, x0: torch.Tensor | None = None, stream=None, fmm=None) -> SolveResult:
+    """FGMRES on the single-layer system; pc is None or a single-layer
+    BlockDiagonal (an FMM plan is refused: it evaluates the double layer)."""
     sigma = torch.zeros_like(f) if x0 is None else x0.clone()
     hist = np.zeros(max_iter + 2)
     kind = 0 if pc is None else 1
     p = GmresParams(tol=tol, max_iter=max_iter, restart=restart, pc=kind,
                     use_x0=int(x0 is not None), bd=pc.h.value if kind == 1 else None, ifmm=None,
-                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                    res_hist=hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    fmm=fmm.h.value if fmm is not None else None)
     r = GmresResult()
     check(load().gmres_solve_slp(ctypes.byref(dg.c), _ptr(f), _ptr(sigma), ctypes.byref(p),
                                  ctypes.byref(r), _stream(stream)))
@@ -567,10 +644,10 @@ def matvec_batched(dgs, xs, mode: int = 0, stream=None):
 
 
 def ifmm_factor_batched(dgs, eps=1e-6, cheb_n=10, leaf_target=64, max_depth=0, precision=0,
-                        workers=4):
+                        workers=4, compress=0):
     """IFMM factorisations of every member, several in flight at once."""
     p = IfmmParams(eps=eps, cheb_n=cheb_n, leaf_target=leaf_target, max_depth=max_depth,
-                   precision=precision)
+                   precision=precision, compress=_compress(compress))
     hs = (ctypes.c_void_p * len(dgs))()
     torch.cuda.synchronize()
     check(load().ifmm_factor_batched(_geom_array(dgs), len(dgs), ctypes.byref(p), hs, workers))

@@ -19,6 +19,11 @@ Stager::~Stager() {
   if (host) (void)hipHostFree(host);
 }
 
+OpFlops &op_flops() {
+  thread_local OpFlops f;
+  return f;
+}
+
 void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
   const size_t need = (bytes + 255) & ~size_t(255);
   if (need > cap) fail(SBIE_OUT_OF_MEMORY, "descriptor batch of %zu bytes exceeds staging", bytes);
@@ -61,77 +66,11 @@ constexpr int kBlockedMin = 48;  // larger matrices use the blocked inverse
 constexpr int kPanel = 32;
 
 // ----------------------------------------------------------------------------
-// GEMM: one 64 x 64 output tile per workgroup, 256 threads, 4 x 4 per thread
+// GEMM: one 64 x 64 output tile per workgroup, 256 threads (four waves, each a
+// 32 x 32 quarter), on the matrix cores
 // ----------------------------------------------------------------------------
-template <class T>
-__global__ __launch_bounds__(256) void gemm_tiles(const GemmDesc<T> *__restrict__ descs,
-                                                  const int2 *__restrict__ tiles) {
-  const int2 tl = tiles[blockIdx.x];
-  const GemmDesc<T> d = descs[tl.x];
-  const int tiles_m = (d.m + 63) >> 6;
-  const int row0 = (tl.y % tiles_m) * 64;
-  const int col0 = (tl.y / tiles_m) * 64;
-  __shared__ T As[16][65];
-  __shared__ T Bs[16][65];
-  const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int k0 = 0; k0 < d.k; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int r, kk;
-      if (!d.ta) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
-      const int gi = row0 + r, gk = k0 + kk;
-      T v = T(0);
-      if (gi < d.m && gk < d.k)
-        v = d.ta ? d.A[gk + (size_t)gi * d.lda] : d.A[gi + (size_t)gk * d.lda];
-      As[kk][r] = v;
-      int c;
-      if (!d.tb) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
-      const int gj = col0 + c, gk2 = k0 + kk;
-      T w = T(0);
-      if (gj < d.n && gk2 < d.k)
-        w = d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb];
-      Bs[kk][c] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = row0 + tr + 16 * i;
-    if (r >= d.m) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = col0 + tc + 16 * j;
-      if (c >= d.n) continue;
-      T *p = d.C + r + (size_t)c * d.ldc;
-      T v = d.alpha * acc[i][j];
-      if (d.beta != T(0)) v = fma(d.beta, *p, v);
-      *p = v;
-    }
-  }
-}
-
-// FP64 GEMM tile on the matrix cores: the same 64 x 64 tiles and LDS staging
-// as gemm_tiles, with each of the four waves computing a 32 x 32 quarter as
+// FP64 GEMM tile: the output tile is staged through LDS in k-slabs of 16,
+// with each of the four waves computing a 32 x 32 quarter as
 // 2 x 2 blocks of v_mfma_f64_16x16x4.  Operand layout of that instruction
 // (checked on the device): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16], and register v of lane l receives D[l / 16 + 4 v][l % 16].
@@ -215,13 +154,217 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *_
       }
 }
 
-// FP64 products go to the matrix cores, FP32 ones to the vector tile.
+// FP32 GEMM tile on the matrix cores: the same 64 x 64 tiles, LDS staging
+// and 2 x 2 blocks per wave as gemm_tiles_mfma, with v_mfma_f32_16x16x4f32
+// (FP32 products accumulated in FP32).  Operand layout as for the FP64
+// instruction (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]); the
+// result layout differs (checked on the device): register v of lane l
+// receives D[4 (l / 16) + v][l % 16].
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gemm_tiles_mfma_f32(const GemmDesc<float> *__restrict__ descs,
+                                                           const int2 *__restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const GemmDesc<float> d = descs[tl.x];
+  const int tiles_m = (d.m + 63) >> 6;
+  const int row0 = (tl.y % tiles_m) * 64;
+  const int col0 = (tl.y / tiles_m) * 64;
+  __shared__ float As[16][65];
+  __shared__ float Bs[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  mfma_f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  float ra[4], rb[4];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int r, kk;
+      if (!d.ta) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
+      const int gi = row0 + r, gk = k0 + kk;
+      ra[q] = (gi < d.m && gk < d.k) ? (d.ta ? d.A[gk + (size_t)gi * d.lda] : d.A[gi + (size_t)gk * d.lda]) : 0.f;
+      int c;
+      if (!d.tb) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
+      const int gj = col0 + c, gk2 = k0 + kk;
+      rb[q] = (gj < d.n && gk2 < d.k) ? (d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb]) : 0.f;
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if (!d.ta) As[e >> 6][e & 63] = ra[q]; else As[e & 15][e >> 4] = ra[q];
+      if (!d.tb) Bs[e & 15][e >> 4] = rb[q]; else Bs[e >> 6][e & 63] = rb[q];
+    }
+  };
+  if (d.k > 0) load_stage(0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    store_stage();
+    __syncthreads();
+    if (k0 + 16 < d.k) load_stage(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[ks + lk][wr + 16 * q + li];
+        b[q] = Bs[ks + lk][wc + 16 * q + li];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + wr + 16 * x + 4 * lk + v;
+        const int c = col0 + wc + 16 * y + li;
+        if (r >= d.m || c >= d.n) continue;
+        float *p = d.C + r + (size_t)c * d.ldc;
+        float val = d.alpha * acc[x][y][v];
+        if (d.beta != 0.f) val = fmaf(d.beta, *p, val);
+        *p = val;
+      }
+}
+
+// Products with FP16 or BF16 inputs on the matrix cores and FP32
+// accumulation (v_mfma_f32_16x16x16f16 / v_mfma_f32_16x16x16bf16_1k), for
+// the Gaussian sketches of the recompression, whose results only have to
+// span the right column space.  alpha is applied to A in the descriptor's
+// precision before the operand is rounded (the callers' alpha is a
+// reciprocal block norm, so the rounded entries stay within FP16's range);
+// the output is the FP32 accumulator widened to T, plus beta C.  Operand
+// layout (checked on the device for both instructions): lane l supplies
+// A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16], q = 0..3; results
+// as for the FP32 instruction, D[4 (l / 16) + v][l % 16].
+typedef _Float16 mfma_h4 __attribute__((ext_vector_type(4)));
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+
+// FP32 to BF16 bits, rounding to nearest even (finite inputs only).
+__device__ __forceinline__ short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+template <class T, GemmInputs L>
+__global__ __launch_bounds__(256) void gemm_tiles_mfma_lowin(const GemmDesc<T> *__restrict__ descs,
+                                                             const int2 *__restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const GemmDesc<T> d = descs[tl.x];
+  const int tiles_m = (d.m + 63) >> 6;
+  const int row0 = (tl.y % tiles_m) * 64;
+  const int col0 = (tl.y / tiles_m) * 64;
+  __shared__ float As[16][65];
+  __shared__ float Bs[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  mfma_f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  float ra[4], rb[4];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int r, kk;
+      if (!d.ta) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
+      const int gi = row0 + r, gk = k0 + kk;
+      ra[q] = (gi < d.m && gk < d.k)
+                  ? (float)(d.alpha * (d.ta ? d.A[gk + (size_t)gi * d.lda] : d.A[gi + (size_t)gk * d.lda]))
+                  : 0.f;
+      int c;
+      if (!d.tb) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
+      const int gj = col0 + c, gk2 = k0 + kk;
+      rb[q] = (gj < d.n && gk2 < d.k) ? (float)(d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb])
+                                      : 0.f;
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if (!d.ta) As[e >> 6][e & 63] = ra[q]; else As[e & 15][e >> 4] = ra[q];
+      if (!d.tb) Bs[e & 15][e >> 4] = rb[q]; else Bs[e >> 6][e & 63] = rb[q];
+    }
+  };
+  if (d.k > 0) load_stage(0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    store_stage();
+    __syncthreads();
+    if (k0 + 16 < d.k) load_stage(k0 + 16);
+    if constexpr (L == GemmInputs::kF16) {
+      mfma_h4 a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          a[q][h] = (_Float16)As[4 * lk + h][wr + 16 * q + li];
+          b[q][h] = (_Float16)Bs[4 * lk + h][wc + 16 * q + li];
+        }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16f16(a[x], b[y], acc[x][y], 0, 0, 0);
+    } else {
+      mfma_s4 a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          a[q][h] = bf16_bits(As[4 * lk + h][wr + 16 * q + li]);
+          b[q][h] = bf16_bits(Bs[4 * lk + h][wc + 16 * q + li]);
+        }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + wr + 16 * x + 4 * lk + v;
+        const int c = col0 + wc + 16 * y + li;
+        if (r >= d.m || c >= d.n) continue;
+        T *p = d.C + r + (size_t)c * d.ldc;
+        T val = (T)acc[x][y][v];
+        if (d.beta != T(0)) val = fma(d.beta, *p, val);
+        *p = val;
+      }
+}
+
+// FP64 and FP32 products go to the matrix cores in their own precision, or
+// with inputs rounded to FP16 or BF16 when the caller asks for it.
 template <class T>
-void launch_gemm_tiles(unsigned nt, const GemmDesc<T> *dd, const int2 *td, hipStream_t s) {
-  if constexpr (std::is_same<T, double>::value)
+void launch_gemm_tiles(unsigned nt, const GemmDesc<T> *dd, const int2 *td, hipStream_t s, GemmInputs in) {
+  if (in == GemmInputs::kF16)
+    gemm_tiles_mfma_lowin<T, GemmInputs::kF16><<<nt, 256, 0, s>>>(dd, td);
+  else if (in == GemmInputs::kBF16)
+    gemm_tiles_mfma_lowin<T, GemmInputs::kBF16><<<nt, 256, 0, s>>>(dd, td);
+  else if constexpr (std::is_same<T, double>::value)
     gemm_tiles_mfma<<<nt, 256, 0, s>>>(dd, td);
   else
-    gemm_tiles<T><<<nt, 256, 0, s>>>(dd, td);
+    gemm_tiles_mfma_f32<<<nt, 256, 0, s>>>(dd, td);
   SBIE_LAUNCH_CHECK();
 }
 
@@ -663,6 +806,190 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_kernel(const PgsDesc<T> *__re
 }
 
 
+// Blocked variant for FP64 (candidates read-only, residual norms downdated):
+// each step takes the (up to) B candidates of largest residual norm at once,
+// projects the block against the columns accepted so far (classical
+// Gram-Schmidt twice, 64 columns at a time), orthonormalises it in LDS in
+// the order of the norms (a candidate whose residual falls to the tolerance
+// inside the block, or into the span, is retired), appends the accepted
+// columns and downdates every remaining candidate's norm by them in one pass
+// over the candidates.  The candidates and the basis are thus read once per
+// block instead of once per column.  The result has the same guarantee as
+// the column-by-column pivoting: on exit every candidate's residual norm is
+// at most the tolerance; the chosen directions may differ within a block.
+constexpr int kPgsChunk = 64;
+
+template <int B>
+__global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<double> *__restrict__ descs) {
+  extern __shared__ unsigned char shraw[];
+  const PgsDesc<double> d = descs[blockIdx.x];
+  double *norms = reinterpret_cast<double *>(shraw);   // c
+  double *Q = norms + d.c;                              // B x m (block columns)
+  __shared__ double dots[kPgsChunk][B];
+  __shared__ double vsel[B], nsq[B];
+  __shared__ int psel[B];
+  __shared__ int nsel, nacc;
+  __shared__ double red_v[kPgsWaves];
+  __shared__ int red_i[kPgsWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = wv; j < d.c; j += kPgsWaves) {
+    const double *col = d.R + (size_t)j * d.ldr;
+    double s = 0.0;
+    for (int i = lane; i < d.m; i += 64) s = fma(col[i], col[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) norms[j] = s;
+  }
+  __syncthreads();
+  const double tol2 = d.tol * d.tol;
+  const int c0 = min(d.orth_from, d.r0);
+  int k = 0;
+  for (int guard = 0; guard < d.c + d.rmax && d.r0 + k < d.rmax; ++guard) {
+    // 1. up to B pivots, largest residual norm first (lowest index on ties)
+    const int room = min(B, d.rmax - d.r0 - k);
+    int ns = 0;
+    for (; ns < room; ++ns) {
+      double best = -1.0;
+      int bi = 0;
+      for (int j = tid; j < d.c; j += kPgsThreads)
+        if (norms[j] > best) { best = norms[j]; bi = j; }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_down(best, o, 64);
+        const int oi = __shfl_down(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[wv] = best; red_i[wv] = bi; }
+      __syncthreads();
+      double vmax = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < kPgsWaves; ++w)
+        if (red_v[w] > vmax || (red_v[w] == vmax && red_i[w] < p)) { vmax = red_v[w]; p = red_i[w]; }
+      __syncthreads();            // everyone has read red_v / red_i
+      if (!(vmax > tol2)) break;  // uniform
+      if (tid == 0) {
+        vsel[ns] = vmax;
+        psel[ns] = p;
+        norms[p] = -1.0;          // taken (restored below if not accepted)
+      }
+      __syncthreads();
+    }
+    if (ns == 0) break;
+    // 2. the block's columns into LDS
+    for (int e = tid; e < ns * d.m; e += kPgsThreads) {
+      const int s = e / d.m, i = e - s * d.m;
+      Q[e] = d.R[i + (size_t)psel[s] * d.ldr];
+    }
+    __syncthreads();
+    // 3. project out the basis columns [c0, r0 + k), twice, 64 at a time
+    const int rc = d.r0 + k;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int cb = c0; cb < rc; cb += kPgsChunk) {
+        const int ce = min(rc, cb + kPgsChunk);
+        for (int col = cb + wv; col < ce; col += kPgsWaves) {
+          const double *w = d.W + (size_t)col * d.ldw;
+          double acc[B];
+#pragma unroll
+          for (int s = 0; s < B; ++s) acc[s] = 0.0;
+          for (int i = lane; i < d.m; i += 64) {
+            const double wi = w[i];
+#pragma unroll
+            for (int s = 0; s < B; ++s)
+              if (s < ns) acc[s] = fma(wi, Q[s * d.m + i], acc[s]);
+          }
+#pragma unroll
+          for (int s = 0; s < B; ++s) {
+            double v = acc[s];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (lane == 0) dots[col - cb][s] = v;
+          }
+        }
+        __syncthreads();
+        for (int e = tid; e < ns * d.m; e += kPgsThreads) {
+          const int s = e / d.m, i = e - s * d.m;
+          double v = Q[e];
+          for (int col = cb; col < ce; ++col) v = fma(-d.W[i + (size_t)col * d.ldw], dots[col - cb][s], v);
+          Q[e] = v;
+        }
+        __syncthreads();
+      }
+    // 4. within the block, in the order of the norms: project against the
+    // block columns accepted before it (twice), accept if its residual is
+    // above the tolerance and not numerically inside the span
+    if (tid == 0) nacc = 0;
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      double *qs = Q + (size_t)s * d.m;
+      const int na = nacc;
+      for (int pass = 0; pass < 2 && na > 0; ++pass) {
+        for (int t = wv; t < na; t += kPgsWaves) {
+          const double *qt = Q + (size_t)t * d.m;
+          double v = 0.0;
+          for (int i = lane; i < d.m; i += 64) v = fma(qt[i], qs[i], v);
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+          if (lane == 0) dots[t][0] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i < d.m; i += kPgsThreads) {
+          double v = qs[i];
+          for (int t = 0; t < na; ++t) v = fma(-Q[(size_t)t * d.m + i], dots[t][0], v);
+          qs[i] = v;
+        }
+        __syncthreads();
+      }
+      double sq = 0.0;
+      for (int i = tid; i < d.m; i += kPgsThreads) sq = fma(qs[i], qs[i], sq);
+      for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
+      if (lane == 0) red_v[wv] = sq;
+      __syncthreads();
+      double nq = 0.0;                       // same values, same order: uniform
+      for (int w = 0; w < kPgsWaves; ++w) nq += red_v[w];
+      __syncthreads();                       // red_v read by everyone
+      const bool take = nq > tol2 && nq > 1e-4 * vsel[s];
+      if (take) {
+        const double inv = 1.0 / sqrt(nq);
+        double *dst = Q + (size_t)na * d.m;  // compact: na <= s
+        for (int i = tid; i < d.m; i += kPgsThreads) dst[i] = qs[i] * inv;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // a column not taken is inside the span or at the tolerance: retired
+        norms[psel[s]] = 0.0;
+        if (take) nacc = na + 1;
+      }
+      __syncthreads();
+    }
+    const int na = nacc;
+    // 5. append the accepted columns, downdate every remaining candidate
+    for (int e = tid; e < na * d.m; e += kPgsThreads) {
+      const int s = e / d.m, i = e - s * d.m;
+      d.W[i + (size_t)(rc + s) * d.ldw] = Q[e];
+    }
+    for (int j = wv; j < d.c && na > 0; j += kPgsWaves) {
+      if (!(norms[j] > tol2)) continue;
+      const double *col = d.R + (size_t)j * d.ldr;
+      double acc[B];
+#pragma unroll
+      for (int s = 0; s < B; ++s) acc[s] = 0.0;
+      for (int i = lane; i < d.m; i += 64) {
+        const double ci = col[i];
+#pragma unroll
+        for (int s = 0; s < B; ++s)
+          if (s < na) acc[s] = fma(Q[s * d.m + i], ci, acc[s]);
+      }
+      double dn = 0.0;
+#pragma unroll
+      for (int s = 0; s < B; ++s) {
+        double v = acc[s];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        dn = fma(v, v, dn);
+      }
+      if (lane == 0) norms[j] -= dn;
+    }
+    k += na;
+    __syncthreads();
+  }
+  if (tid == 0) *d.count = k;
+}
+
 // ----------------------------------------------------------------------------
 // Blocked Gauss-Jordan with partial pivoting by columns, helper kernels.
 // The matrices are column-major, so pivoting by columns makes every
@@ -1047,7 +1374,13 @@ __global__ void splitk_reduce(const T *__restrict__ part, int P, int m, int n, T
 }
 
 template <class T>
-void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) {
+void gemm_batched_impl(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s, GemmInputs in) {
+  OpFlops &fl = op_flops();
+  for (const auto &g : d)
+    if (g.m > 0 && g.n > 0 && g.k > 0) {
+      fl.gemm += 2.0 * g.m * g.n * g.k;
+      ++fl.gemm_products;
+    }
   // A batch with few output tiles but a long inner dimension would leave
   // most compute units idle while a handful of workgroups walk the whole k
   // range: such products are split along k into partial products (written
@@ -1114,7 +1447,7 @@ void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) 
     std::vector<void *> dev;
     st.put_many({{keep.data(), keep.size() * sizeof(GemmDesc<T>)}, {tiles.data() + t0, nt * sizeof(int2)}},
                 dev, s);
-    launch_gemm_tiles<T>((unsigned)nt, (const GemmDesc<T> *)dev[0], (const int2 *)dev[1], s);
+    launch_gemm_tiles<T>((unsigned)nt, (const GemmDesc<T> *)dev[0], (const int2 *)dev[1], s, in);
   }
   for (const auto &sp : splits) {
     const int64_t e = (int64_t)sp.g.m * sp.g.n;
@@ -1122,6 +1455,20 @@ void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) 
                                                      sp.g.ldc, sp.g.beta);
     SBIE_LAUNCH_CHECK();
   }
+}
+
+template <class T>
+void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s) {
+  gemm_batched_impl<T>(d, st, s, GemmInputs::kWorking);
+}
+
+template <class T>
+void gemm_batched_sketch(const std::vector<GemmDesc<T>> &d, GemmInputs in, Stager &st, hipStream_t s) {
+  OpFlops &fl = op_flops();
+  if (in != GemmInputs::kWorking)
+    for (const auto &g : d)
+      if (g.m > 0 && g.n > 0 && g.k > 0) fl.gemm_low += 2.0 * g.m * g.n * g.k;
+  gemm_batched_impl<T>(d, st, s, in);
 }
 
 template <class T, class TA>
@@ -1337,6 +1684,8 @@ template <class T>
 void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                      int32_t *info_dev, Stager &st, hipStream_t s) {
   if (ptrs.empty()) return;
+  for (int n : ns) op_flops().inverse += 2.0 * n * n * (double)n;
+  op_flops().inverses += (int64_t)ns.size();
   int mx = 1;
   for (int n : ns) mx = std::max(mx, n);
   const size_t shmem = 2 * mx * sizeof(T) + mx * sizeof(int);
@@ -1366,6 +1715,9 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     if (ns[i] <= kBlockedMin) { sp.push_back(ptrs[i]); sn.push_back(ns[i]); sidx.push_back(i); }
     else { bp.push_back(ptrs[i]); bn.push_back(ns[i]); bidx.push_back(i); }
   }
+  // the small ones are counted by inverse_batched
+  for (int n : bn) op_flops().inverse += 2.0 * n * n * (double)n;
+  op_flops().inverses += (int64_t)bn.size();
   const int nbm = (int)bp.size();
   const int nb = kPanel;
   int maxn = 0;
@@ -1518,7 +1870,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     };
     auto gemm_step = [&](const GemmPrep &g) {
       if (g.nt == 0) return;
-      launch_gemm_tiles<T>(g.nt, (const GemmDesc<T> *)(db + g.d), (const int2 *)(db + g.t), s);
+      launch_gemm_tiles<T>(g.nt, (const GemmDesc<T> *)(db + g.d), (const int2 *)(db + g.t), s, GemmInputs::kWorking);
     };
     for (size_t it = 0; it < steps.size(); ++it) {
       const Step &q = steps[it];
@@ -1625,6 +1977,23 @@ void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s) {
   if (shmem > 60 * 1024)
     fail(SBIE_UNSUPPORTED, "rank-revealing step too large (%zu bytes of LDS)", shmem);
   auto *dd = (const PgsDesc<T> *)st.put(d.data(), d.size() * sizeof(PgsDesc<T>), s);
+  if constexpr (std::is_same<T, double>::value) {
+    // blocked pivoting: as many block columns (up to 8) as the LDS holds
+    int cmax = 0, mmax = 1;
+    for (const auto &p : d) { cmax = std::max(cmax, p.c); mmax = std::max(mmax, p.m); }
+    const size_t room = (size_t)48 * 1024 - (size_t)cmax * sizeof(double);
+    const int b = (int)std::min<size_t>(8, room / ((size_t)mmax * sizeof(double)));
+    if (b >= 4) {
+      const size_t sh = (size_t)cmax * sizeof(double) + (size_t)b * mmax * sizeof(double);
+      if (b >= 8)
+        pgs_block_kernel<8><<<(unsigned)d.size(), kPgsThreads, sh, s>>>(dd);
+      else
+        pgs_block_kernel<4><<<(unsigned)d.size(), kPgsThreads, (size_t)cmax * sizeof(double) +
+                              (size_t)4 * mmax * sizeof(double), s>>>(dd);
+      SBIE_LAUNCH_CHECK();
+      return;
+    }
+  }
   pgs_kernel<T><<<(unsigned)d.size(), kPgsThreads, shmem, s>>>(dd);
   SBIE_LAUNCH_CHECK();
 }
@@ -1652,6 +2021,7 @@ void convert(const A *src, B *dst, size_t n, hipStream_t s) {
 
 #define SBIE_INST(T)                                                                     \
   template void gemm_batched<T>(const std::vector<GemmDesc<T>> &, Stager &, hipStream_t); \
+  template void gemm_batched_sketch<T>(const std::vector<GemmDesc<T>> &, GemmInputs, Stager &, hipStream_t); \
   template void gemv_batched<T>(const std::vector<GemvDesc<T>> &,                        \
                                 const std::vector<GemvTerm<T>> &, Stager &, hipStream_t); \
   template void gemv_launch<T, T>(const GemvDesc<T> *, const GemvTerm<T, T> *, int, int, \

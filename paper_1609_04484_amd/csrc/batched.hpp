@@ -73,8 +73,24 @@ struct Stager {
   void reset() { used = 0; }
 };
 
+// Algorithmic flop counts of the batched products and inverses issued by the
+// calling thread (GEMM 2 m n k; Gauss-Jordan inverse 2 n^3), the op log of
+// a factorisation.  Reset and read by its caller.
+struct OpFlops {
+  double gemm = 0.0, inverse = 0.0;
+  double gemm_low = 0.0;   // the part of gemm run with FP16/BF16 inputs
+  int64_t gemm_products = 0, inverses = 0;
+};
+OpFlops &op_flops();
+
 template <class T>
 void gemm_batched(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s);
+// Products whose result only has to span the right subspace (randomised
+// sketches): kF16 / kBF16 round the inputs (after alpha) to FP16 / BF16 and
+// accumulate in FP32 on the matrix cores; kWorking is gemm_batched.
+enum class GemmInputs : int { kWorking = 0, kF16 = 1, kBF16 = 2 };
+template <class T>
+void gemm_batched_sketch(const std::vector<GemmDesc<T>> &d, GemmInputs in, Stager &st, hipStream_t s);
 template <class T>
 void gemv_batched(const std::vector<GemvDesc<T>> &d, const std::vector<GemvTerm<T>> &t,
                   Stager &st, hipStream_t s);

@@ -148,8 +148,25 @@ struct MatvecWork {
 MatvecWork plan_matvec(const sbie_geom *g);
 size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g);
 void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base);
+// An alternative evaluation of the double-layer pair sum (the fast multipole
+// method, fmm.hip): from the packed source records (8 doubles per node:
+// x, y, q_xx, q_xy, q_yy, with q_xy the sum of both off-diagonal entries of
+// w/pi n sigma^T) it writes part[0..nn) and part[nn..2nn), the x and y
+// components of the pair sum at every node (the plain mode's layout).
+struct PairSum {
+  virtual ~PairSum() = default;
+  virtual void run(const double *src, double *part, hipStream_t s) const = 0;
+};
+
+// The pair sum of a fast-multipole plan (fmm.hip), and whether the plan was
+// built for this geometry (same node arrays and counts).
+const PairSum *fmm_pair_sum(const sbie_fmm *f);
+bool fmm_same_geometry(const sbie_fmm *f, const sbie_geom *g);
+
+// y = A x.  With `pairs` set, that evaluation replaces the direct pair
+// kernel (plain modes only; w.chunks must be 1).
 void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
-                MatvecWork &w, hipStream_t s);
+                MatvecWork &w, hipStream_t s, const PairSum *pairs = nullptr);
 
 // Wall length |Gamma_0| into *out (device scalar).
 void wall_length(const sbie_geom *g, double *out, hipStream_t s);

@@ -341,8 +341,18 @@ int gmres_run(const sbie_geom *g, const double *f, double *x,
   MatvecWork mw = plan_matvec(g);
   DevBuf<double> mvs(matvec_scratch_doubles(mw, g));
   bind_matvec_scratch(mw, g, mvs.p);
+  // with a fast-multipole plan: its pair sum in the Arnoldi products (one
+  // partial sum), the direct compensated product for true residuals
+  const PairSum *fmm = p->fmm ? fmm_pair_sum(p->fmm) : nullptr;
+  MatvecWork mf = plan_matvec(g);
+  mf.chunks = 1;
+  DevBuf<double> mfs(fmm ? matvec_scratch_doubles(mf, g) : 0);
+  if (fmm) bind_matvec_scratch(mf, g, mfs.p);
   KrylovOp op{n_unknowns(g), [&](const double *in, double *out, bool accurate, hipStream_t st) {
-                matvec_run(g, in, out, accurate ? SBIE_MV_FULL_ACCURATE : SBIE_MV_FULL, mw, st);
+                if (fmm && !accurate)
+                  matvec_run(g, in, out, SBIE_MV_FULL, mf, st, fmm);
+                else
+                  matvec_run(g, in, out, accurate ? SBIE_MV_FULL_ACCURATE : SBIE_MV_FULL, mw, st);
               }};
   return gmres_run_op(op, f, x, p, res, s);
 }
@@ -371,6 +381,8 @@ extern "C" int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
     if (f < sigma + n && sigma < f + n) sbie::fail(SBIE_INVALID_ARGUMENT, "f and sigma overlap");
     if (p->pc == 1 && sbie::bd_size(p->bd) != n)
       sbie::fail(SBIE_INVALID_ARGUMENT, "the block-diagonal handle belongs to another operator or geometry");
+    if (p->fmm && !sbie::fmm_same_geometry(p->fmm, g))
+      sbie::fail(SBIE_INVALID_ARGUMENT, "the fast-multipole plan belongs to another geometry");
     sbie::validate_geom_device(g, (hipStream_t)stream);
     *res = gmres_result{};
     return sbie::gmres_run(g, f, sigma, p, res, (hipStream_t)stream);
@@ -385,6 +397,7 @@ extern "C" int gmres_solve_slp(const sbie_geom *g, const double *f, double *sigm
     if (p->max_iter < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "max_iter < 0");
     if (!(p->tol > 0.0)) sbie::fail(SBIE_INVALID_ARGUMENT, "tol must be positive");
     if (p->pc == 2) sbie::fail(SBIE_UNSUPPORTED, "the IFMM preconditioner is built for the double layer only");
+    if (p->fmm) sbie::fail(SBIE_UNSUPPORTED, "the fast-multipole plan evaluates the double layer only");
     if (p->pc < 0 || p->pc > 1) sbie::fail(SBIE_INVALID_ARGUMENT, "unknown preconditioner %d", p->pc);
     if (p->pc == 1 && !p->bd) sbie::fail(SBIE_INVALID_ARGUMENT, "pc=1 needs a block-diagonal handle");
     const int64_t n = 2 * g->n_nodes;

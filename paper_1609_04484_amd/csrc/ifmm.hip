@@ -780,6 +780,11 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   n = n_unknowns(g);
   const double eps = prm->eps;
   const int cn = prm->cheb_n;
+  // inputs of the two sketch products of the recompression (the far
+  // fill-ins times a Gaussian matrix, the wide candidate sets times a
+  // Gaussian matrix): the factor's precision, or FP16 / BF16 on the matrix
+  // cores with FP32 accumulation
+  const GemmInputs sketch_in = (GemmInputs)prm->compress;
   const int n2 = cn * cn;
   if (cn < 2 || cn > 24) fail(SBIE_INVALID_ARGUMENT, "cheb_n must be in [2, 24]");
   if (!(eps > 0.0 && eps < 1.0)) fail(SBIE_INVALID_ARGUMENT, "eps must be in (0, 1)");
@@ -795,6 +800,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     SBIE_HIP(hipMemcpy(rad.data(), g->radius, m_p * 8, hipMemcpyDeviceToHost));
   }
   StageClock clk(s);
+  op_flops() = OpFlops{};
   HTree tr = build_tree(px, py, nn, g->curve_off[m_p], leaf_target, prm->max_depth);
   clk.tick("tree");
   const double leaf_h = tr.lv[tr.depth].h;
@@ -1302,7 +1308,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         for (size_t a = 0; a < aug.size(); ++a) aug[a].c = fillc[a];
       }
       copy_batched<T>(cc, st, s);
-      gemm_batched<T>(gd, st, s);
+      gemm_batched_sketch<T>(gd, sketch_in, st, s);
       clk.tick("elim_fillins");
       //   project out the current basis twice: P = W^T C, C -= W P
       for (int pass = 0; pass < 2; ++pass) {
@@ -1335,7 +1341,23 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
           gsk.push_back({m[j], kPgsSketch, aug[a].c, 0, 0, aug[a].cand, m[j], om, cmax, ysk[a], m[j],
                          T(1.0 / std::sqrt((double)kPgsSketch)), T(0)});
         }
-        gemm_batched<T>(gsk, st, s);
+        gemm_batched_sketch<T>(gsk, sketch_in, st, s);
+        if (sketch_in != GemmInputs::kWorking) {
+          // rounding the projected candidates to FP16 / BF16 brings back
+          // components along the current basis of the size of the unit
+          // roundoff; the pivoted Gram-Schmidt below assumes there are none,
+          // so the sketch is projected once more in the factor's precision
+          std::vector<GemmDesc<T>> g1, g2;
+          for (size_t a = 0; a < aug.size(); ++a) {
+            const int j = aug[a].j;
+            if (!ysk[a] || r[j] == 0) continue;
+            T *pp = pa.get<T>((size_t)r[j] * kPgsSketch);
+            g1.push_back({r[j], kPgsSketch, m[j], 1, 0, W[j], m[j], ysk[a], m[j], pp, r[j], T(1), T(0)});
+            g2.push_back({m[j], kPgsSketch, r[j], 0, 0, W[j], m[j], pp, r[j], ysk[a], m[j], T(-1), T(1)});
+          }
+          gemm_batched<T>(g1, st, s);
+          gemm_batched<T>(g2, st, s);
+        }
       }
       std::vector<PgsDesc<T>> pd;
       for (size_t a = 0; a < aug.size(); ++a) {
@@ -1580,6 +1602,9 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   stats.factor_bytes = (int64_t)persist.total;
   stats.factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  stats.gemm_flops = op_flops().gemm;
+  stats.gemm_low_flops = op_flops().gemm_low;
+  stats.inverse_flops = op_flops().inverse;
 }
 
 }  // namespace
@@ -1600,6 +1625,9 @@ ifmm_handle *ifmm_factor_internal(const sbie_geom *g, const ifmm_params *p, hipS
                                   bool defer_graph) {
   validate_geom(g);
   if (!p) fail(SBIE_INVALID_ARGUMENT, "null pointer");
+  if (p->reserved != 0) fail(SBIE_INVALID_ARGUMENT, "ifmm_params.reserved must be 0");
+  if (p->compress < 0 || p->compress > 2)
+    fail(SBIE_INVALID_ARGUMENT, "compress must be 0 (factor precision), 1 (FP16 inputs) or 2 (BF16 inputs)");
   validate_geom_device(g, s);
   auto h = std::make_unique<ifmm_handle>();
   if (p->precision == 0 || p->precision == 2) {

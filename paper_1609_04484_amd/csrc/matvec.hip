@@ -23,6 +23,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "pairmath.hpp"
 
 namespace sbie {
 
@@ -112,25 +113,6 @@ __global__ void wall_flux(int64_t wall_start, int64_t nn,
                           const double *__restrict__ u, double *scal,
                           int with_flux) {
   wall_flux_body(wall_start, nn, nx, ny, w, u, scal, with_flux);
-}
-
-// s + c += x with the rounding error of the addition carried in c (Knuth's
-// two-sum): used by the compensated mode, whose residuals must resolve
-// 1e-10 of the data when the density is much larger than the data.
-__device__ __forceinline__ void two_sum_acc(double &s, double &c, double x) {
-#pragma clang fp contract(off)
-  const double t = s + x;
-  const double bp = t - s;
-  c += (s - (t - bp)) + (x - bp);
-  s = t;
-}
-
-// 1/d to full FP64 precision: hardware reciprocal estimate refined by one
-// third-order Newton step, r' = r (1 + e + e^2) with e = 1 - d r.
-__device__ __forceinline__ double recip(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  return fma(r, fma(e, e, e), r);
 }
 
 // Reciprocals of T positive numbers with one hardware reciprocal: the
@@ -606,11 +588,13 @@ void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
 }
 
 void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
-                MatvecWork &w, hipStream_t s) {
+                MatvecWork &w, hipStream_t s, const PairSum *pairs) {
   const int64_t nn = g->n_nodes;
   const int m = g->n_pores;
   const int full = mode == SBIE_MV_FULL || mode == SBIE_MV_FULL_ACCURATE;
   const bool acc = mode == SBIE_MV_FULL_ACCURATE;
+  if (pairs && (acc || w.chunks != 1))
+    fail(SBIE_UNSUPPORTED, "the fast multipole pair sum has no compensated mode");
   const int64_t wall_start = g->curve_off[m];
   const int64_t packn = nn > m ? nn : m;
   pack_sources<<<ceil_div(packn, 256), 256, 0, s>>>(
@@ -636,7 +620,9 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
     SBIE_HIP(hipEventCreate(&ev1));
     SBIE_HIP(hipEventRecord(ev0, s));
   }
-  if (acc) {
+  if (pairs) {
+    pairs->run(w.src, w.part, s);
+  } else if (acc) {
     dlp_pairs<1, true><<<grid1, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles1, xcd);
   } else {
     switch (w.tpt) {

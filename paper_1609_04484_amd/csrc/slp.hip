@@ -21,6 +21,7 @@
 #include <cmath>
 #include <utility>
 
+#include "pairmath.hpp"
 #include "slp.hpp"
 
 namespace sbie {
@@ -102,20 +103,6 @@ __device__ __forceinline__ int curve_of(const int64_t *__restrict__ off, int ncu
     if (off[mid] <= i) lo = mid; else hi = mid - 1;
   }
   return lo;
-}
-
-__device__ __forceinline__ void two_sum_acc(double &s, double &c, double x) {
-#pragma clang fp contract(off)
-  const double t = s + x;
-  const double bp = t - s;
-  c += (s - (t - bp)) + (x - bp);
-  s = t;
-}
-
-__device__ __forceinline__ double recip(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  return fma(r, fma(e, e, e), r);
 }
 
 __global__ void slp_pack(int64_t nn, const double *__restrict__ x, const double *__restrict__ y,

@@ -106,6 +106,44 @@ def test_gmres_with_ifmm_matches_lu(lib, tiny, precision):
     assert r.iters <= ref.iters + 3
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("compress", ["fp16", "bf16"])
+def test_low_precision_sketches(lib, tiny, precision, compress):
+    """FP16 / BF16 inputs (FP32 accumulation on the matrix cores) for the two
+    Gaussian-sketch products of the recompression.  Rounding a norm-scaled
+    block perturbs it by about the format's unit roundoff, so at eps = 1e-3
+    one application stays within the eps bound of the working-precision
+    sketches (5e-2 against LU), and FGMRES reaches the LU solution to the
+    same tolerance in about as many iterations.  The flop log shows that the
+    low-precision products ran."""
+    g, a, f, sig = tiny
+    dg = lib.DeviceGeometry(g)
+    base = lib.IFMM(dg, eps=1e-3, cheb_n=6, precision=precision)
+    p = lib.IFMM(dg, eps=1e-3, cheb_n=6, precision=precision, compress=compress)
+    st, st0 = p.stats(), base.stats()
+    print(compress, "low-precision flops", st["gemm_low_flops"], "of", st["gemm_flops"])
+    assert st0["gemm_low_flops"] == 0.0
+    assert 0.0 < st["gemm_low_flops"] < st["gemm_flops"]
+    x = p.solve(dg.vector(f)).cpu().numpy()
+    assert rel(x, sig) < 5e-2
+    r0 = lib.gmres(dg, dg.vector(f), pc=base, tol=1e-12)
+    r = lib.gmres(dg, dg.vector(f), pc=p, tol=1e-12)
+    print("iterations working", r0.iters, compress, r.iters)
+    assert r.status == 0
+    xs = r.sigma.cpu().numpy()
+    assert np.linalg.norm(f - a @ xs) / np.linalg.norm(f) < 1e-12
+    assert rel(xs, sig) < 1e-8
+    assert r.iters <= r0.iters + 3
+
+
+def test_compress_argument_checked(lib, tiny):
+    g = tiny[0]
+    dg = lib.DeviceGeometry(g)
+    with pytest.raises(lib.SbieError) as e:
+        lib.IFMM(dg, eps=1e-3, cheb_n=6, compress=3)
+    assert e.value.code == -1
+
+
 def test_ifmm_beats_block_diagonal_iterations(lib):
     g = make_geometry(dict(length=10.0, n_ext=2048, n_pores=100, r_lo=0.02, r_hi=0.05,
                            n_int=64, gap_pore=0.005, gap_wall=0.1), 3)
@@ -113,9 +151,12 @@ def test_ifmm_beats_block_diagonal_iterations(lib):
     dg = lib.DeviceGeometry(g)
     r_bd = lib.gmres(dg, dg.vector(f), pc=lib.BlockDiagonal(dg), tol=1e-10)
     r_if = lib.gmres(dg, dg.vector(f), pc=lib.IFMM(dg, eps=1e-3, cheb_n=6), tol=1e-10)
-    print("iterations bd", r_bd.iters, "ifmm", r_if.iters)
-    assert r_if.status == 0 and r_bd.status == 0
+    r_16 = lib.gmres(dg, dg.vector(f), pc=lib.IFMM(dg, eps=1e-3, cheb_n=6, precision=1, compress="fp16"),
+                     tol=1e-10)
+    print("iterations bd", r_bd.iters, "ifmm", r_if.iters, "ifmm fp32 + fp16 sketches", r_16.iters)
+    assert r_if.status == 0 and r_bd.status == 0 and r_16.status == 0
     assert r_if.iters < r_bd.iters / 4
+    assert r_16.iters < r_bd.iters / 4
 
 
 def test_ifmm_graph_replay_matches_eager(lib, tiny, monkeypatch):
