@@ -76,6 +76,7 @@ def cpu_baseline(g, f, bd_iters):
 
     solves/s = 1 / (factor + iterations x (operator + apply + Arnoldi)), with
     the iteration count the same algorithm needs for this pipe on the GPU."""
+    import numpy as np
     import scipy.linalg as sla
     import threadpoolctl
     from oracle import capply, dlp, solve
@@ -134,9 +135,10 @@ def cpu_baseline(g, f, bd_iters):
 
 
 def fmm_comparison(lib, dg, n, orders=(8, 10, 12, 14)):
-    """The fast-multipole product against the direct one on the bench pipe:
-    plan time (host), time per product (HIP events, 10 products) and the
-    largest difference relative to the largest entry of the direct result."""
+    """The fast-multipole product against the direct one on the bench pipe,
+    on the uniform tree ("orders") and the adaptive one ("adaptive"): plan
+    time (host), time per product (HIP events, 10 products) and the largest
+    difference relative to the largest entry of the direct result."""
     import numpy as np
     import torch
     x = dg.vector(np.random.default_rng(11).standard_normal(n))
@@ -156,14 +158,17 @@ def fmm_comparison(lib, dg, n, orders=(8, 10, 12, 14)):
     t_direct = timed(lambda: lib.matvec(dg, x, out=direct))
     out = {"direct_ms": t_direct, "orders": {}}
     y = torch.empty_like(x)
-    for p in orders:
-        t0 = time.perf_counter()
-        fm = lib.FMM(dg, cheb_n=p)
-        t_plan = time.perf_counter() - t0
-        ms = timed(lambda: fm.matvec(x, out=y))
-        err = float((y - direct).abs().max() / direct.abs().max())
-        out["orders"][p] = {"ms": ms, "plan_s": t_plan, "rel_diff_vs_direct": err, **fm.stats()}
-        fm.close()
+    for adaptive in (False, True):
+        key = "adaptive" if adaptive else "orders"
+        out.setdefault(key, {})
+        for p in orders:
+            t0 = time.perf_counter()
+            fm = lib.FMM(dg, cheb_n=p, leaf_target=48 if adaptive else 64, adaptive=adaptive)
+            t_plan = time.perf_counter() - t0
+            ms = timed(lambda: fm.matvec(x, out=y))
+            err = float((y - direct).abs().max() / direct.abs().max())
+            out[key][p] = {"ms": ms, "plan_s": t_plan, "rel_diff_vs_direct": err, **fm.stats()}
+            fm.close()
     return out
 
 

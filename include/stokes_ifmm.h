@@ -312,12 +312,15 @@ int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
  * Fast multipole evaluation of the double-layer pair sum (Section 2.2: the
  * matrix-vector products of GMRES can be computed by a fast multipole
  * method in O(N) work).  Black-box FMM with Chebyshev interpolation (the
- * far-field approximation of Section 3.1's H^2 operators): a uniform
- * quadtree on the bounding square of the nodes (non-empty boxes only),
- * cheb_n x cheb_n tensor Chebyshev grids per box carrying the multipole
- * tensors of the sources and the local velocities, interaction lists of
- * the well-separated boxes (children of the parent's neighbours that do
- * not touch the box) and direct sums between touching leaves.  Only the
+ * far-field approximation of Section 3.1's H^2 operators): a quadtree on
+ * the bounding square of the nodes (non-empty boxes only), uniform or
+ * adaptive, with cheb_n x cheb_n tensor Chebyshev grids per box carrying
+ * the multipole tensors of the sources and the local velocities.  Lists:
+ * V (children of the parent's neighbours that do not touch the box:
+ * multipole to local), U (leaves touching a leaf: direct sum), and on an
+ * adaptive tree W (boxes smaller than a leaf that do not touch it but whose
+ * parents do: multipole evaluated at the leaf's nodes) and X (the inverse
+ * of W: a larger leaf's sources into the box's local expansion).  Only the
  * pair sum sum_{j != i} w_j (1/pi) (r.n_j) r r^T / rho^4 sigma_j changes;
  * every other term of the operator is evaluated as in stokes_dlp_matvec.
  * The error is that of the interpolation: it falls geometrically with
@@ -326,10 +329,13 @@ int gmres_solve(const sbie_geom *g, const double *f, double *sigma,
  * at 14, 1.2e-11 at 16); a quadtree of depth 0 or 1 has no far field and
  * gives the direct sum.
  *   cheb_n       Chebyshev nodes per direction: 4, 6, ..., 16.
- *   leaf_target  with max_depth = 0: the shallowest depth whose non-empty
- *                leaves hold at most this many nodes on average (0 = 64).
- *   max_depth    the quadtree depth (0 = from leaf_target; at most 20).
- *   reserved     must be 0.
+ *   leaf_target  uniform tree with max_depth = 0: the shallowest depth whose
+ *                non-empty leaves hold at most this many nodes on average;
+ *                adaptive tree: every box holding more nodes than this is
+ *                split (0 = 64).
+ *   max_depth    uniform: the quadtree depth (0 = from leaf_target);
+ *                adaptive: the deepest level allowed (0 = 20); at most 20.
+ *   adaptive     0 = uniform depth, 1 = adaptive.
  * fmm_plan builds the tree and its lists on the host from the node
  * positions (read once from the device; synchronises) and keeps a copy of
  * the geometry descriptor: the geometry's arrays must outlive the plan, and
@@ -339,22 +345,26 @@ typedef struct {
   int32_t cheb_n;
   int32_t leaf_target;
   int32_t max_depth;
-  int32_t reserved;
+  int32_t adaptive;
 } fmm_params;
 int fmm_plan(const sbie_geom *g, const fmm_params *p, sbie_fmm **out, void *stream);
 /* y = A x as stokes_dlp_matvec with the pair sum from the plan; modes
  * SBIE_MV_FULL and SBIE_MV_DLP_ONLY (SBIE_MV_FULL_ACCURATE: SBIE_UNSUPPORTED). */
 int stokes_dlp_matvec_fmm(const sbie_fmm *plan, const double *x, double *y, int mode,
                           void *stream);
-/* Shape of a plan (host): depth, non-empty leaves, boxes over all levels,
- * box pairs in the interaction lists and node pairs summed directly. */
+/* Shape of a plan (host): depth (deepest level), non-empty leaves, boxes
+ * over all levels, the shallowest leaf level, box pairs in the V lists,
+ * node pairs summed directly (U lists), (leaf, box) pairs in the W lists and
+ * (box, leaf) pairs in the X lists. */
 typedef struct {
   int32_t depth;
   int32_t leaves;
   int32_t boxes;
-  int32_t reserved;
+  int32_t min_leaf_level;
   int64_t m2l_box_pairs;
   int64_t near_node_pairs;
+  int64_t m2p_box_pairs;
+  int64_t p2l_box_pairs;
 } fmm_stats;
 int fmm_get_stats(const sbie_fmm *plan, fmm_stats *s);
 int fmm_destroy(sbie_fmm *plan);

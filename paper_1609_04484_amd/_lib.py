@@ -88,7 +88,7 @@ class FmmParams(ctypes.Structure):
         ("cheb_n", ctypes.c_int32),
         ("leaf_target", ctypes.c_int32),
         ("max_depth", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("adaptive", ctypes.c_int32),
     ]
 
 
@@ -97,9 +97,11 @@ class FmmStats(ctypes.Structure):
         ("depth", ctypes.c_int32),
         ("leaves", ctypes.c_int32),
         ("boxes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("min_leaf_level", ctypes.c_int32),
         ("m2l_box_pairs", ctypes.c_int64),
         ("near_node_pairs", ctypes.c_int64),
+        ("m2p_box_pairs", ctypes.c_int64),
+        ("p2l_box_pairs", ctypes.c_int64),
     ]
 
 
@@ -437,9 +439,11 @@ class FMM:
     """Fast-multipole plan of a geometry (Chebyshev interpolation on a
     uniform quadtree) for the double-layer pair sum."""
 
-    def __init__(self, dg: DeviceGeometry, cheb_n=12, leaf_target=64, max_depth=0, stream=None):
+    def __init__(self, dg: DeviceGeometry, cheb_n=12, leaf_target=64, max_depth=0, adaptive=False,
+                 stream=None):
         self.dg = dg
-        p = FmmParams(cheb_n=cheb_n, leaf_target=leaf_target, max_depth=max_depth)
+        p = FmmParams(cheb_n=cheb_n, leaf_target=leaf_target, max_depth=max_depth,
+                      adaptive=int(adaptive))
         h = ctypes.c_void_p()
         check(load().fmm_plan(ctypes.byref(dg.c), ctypes.byref(p), ctypes.byref(h), _stream(stream)))
         self.h = h
@@ -452,7 +456,7 @@ class FMM:
     def stats(self) -> dict:
         s = FmmStats()
         check(load().fmm_get_stats(self.h, ctypes.byref(s)))
-        return {k: getattr(s, k) for k, _ in FmmStats._fields_ if k != "reserved"}
+        return {k: getattr(s, k) for k, _ in FmmStats._fields_}
 
     def close(self):
         if self.h:

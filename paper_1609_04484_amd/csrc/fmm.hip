@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "fmm_tree.hpp"
 #include "pairmath.hpp"
 
 struct sbie_fmm;
@@ -43,7 +44,6 @@ namespace {
 
 constexpr int kFmmThreads = 256;
 constexpr int kLeafThreads = 64;
-constexpr int kMaxDepth = 20;
 
 // S_k(t), k = 0..P-1, for one coordinate t in [-1, 1]; tm[k * P + m] =
 // T_m(t_k).
@@ -94,7 +94,8 @@ __global__ void fmm_gather(int64_t nn, const int *__restrict__ perm, const doubl
 
 // One workgroup per leaf; thread b < P^2 owns multipole node b = by P + bx.
 template <int P>
-__global__ __launch_bounds__(kFmmThreads) void fmm_p2m(int64_t nn, int leaf0, const int *__restrict__ leaf_start,
+__global__ __launch_bounds__(kFmmThreads) void fmm_p2m(int64_t nn, const int *__restrict__ leaf_box,
+                                                       const int *__restrict__ leaf_start,
                                                        const double *__restrict__ ctr, const double *__restrict__ hb,
                                                        const double *__restrict__ tm, const double *__restrict__ srt,
                                                        double *__restrict__ Q) {
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kFmmThreads) void fmm_p2m(int64_t nn, int leaf0, co
   __shared__ double stm[P * P];
   __shared__ double sx[kChunk][P], sy[kChunk][P];
   __shared__ double sq[3][kChunk];
-  const int leaf = blockIdx.x, box = leaf0 + leaf, tid = threadIdx.x;
+  const int leaf = blockIdx.x, box = leaf_box[leaf], tid = threadIdx.x;
   for (int e = tid; e < P * P; e += blockDim.x) stm[e] = tm[e];
   const double cx = ctr[2 * box], cy = ctr[2 * box + 1], ih = 1.0 / hb[box];
   const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
@@ -146,7 +147,8 @@ __global__ __launch_bounds__(kFmmThreads) void fmm_p2m(int64_t nn, int leaf0, co
   }
 }
 
-// Parent multipole from its (up to four) children, boxes [b0, b0 + grid).
+// Parent multipole from its (up to four) children, boxes [b0, b0 + grid);
+// leaves of the level (no children) keep the multipole of their sources.
 // m2[(q P + K) P + m] = S_K((t_m + 2q - 1) / 2): child node m of the lower
 // (q = 0) or upper (q = 1) half in the parent's coordinate.
 template <int P>
@@ -156,6 +158,8 @@ __global__ __launch_bounds__(kFmmThreads) void fmm_m2m(int b0, const int *__rest
   __shared__ double qc[3][P * P];
   __shared__ double tt[3][P * P];
   const int box = b0 + blockIdx.x, tid = threadIdx.x;
+  if (child[4 * box] < 0 && child[4 * box + 1] < 0 && child[4 * box + 2] < 0 && child[4 * box + 3] < 0)
+    return;   // a leaf (uniform over the workgroup)
   for (int e = tid; e < 2 * P * P; e += blockDim.x) sm[e] = m2[e];
   double acc[3] = {0.0, 0.0, 0.0};
   for (int q = 0; q < 4; ++q) {
@@ -240,6 +244,46 @@ __global__ __launch_bounds__(kFmmThreads) void fmm_m2l(int b0, const int *__rest
   }
 }
 
+// Local expansions of the boxes xbox[0..grid) += the direct sum of the
+// sources of their X lists (leaves larger than the box, adjacent to its
+// parent but well separated from the box itself).
+template <int P>
+__global__ __launch_bounds__(kFmmThreads) void fmm_p2l(int64_t nn, const int *__restrict__ xbox,
+                                                       const int *__restrict__ xl_off, const int *__restrict__ xl,
+                                                       const int *__restrict__ leaf_start,
+                                                       const double *__restrict__ ctr, const double *__restrict__ hb,
+                                                       const double *__restrict__ tn, const double *__restrict__ srt,
+                                                       double *__restrict__ Lc) {
+  __shared__ double ss[5][kFmmThreads];
+  const int box = xbox[blockIdx.x], tid = threadIdx.x;
+  const double h = hb[box];
+  double xi = 0.0, yi = 0.0;
+  if (tid < P * P) {
+    xi = fma(h, tn[tid % P], ctr[2 * box]);
+    yi = fma(h, tn[tid / P], ctr[2 * box + 1]);
+  }
+  double ax = 0.0, ay = 0.0;
+  for (int v = xl_off[blockIdx.x]; v < xl_off[blockIdx.x + 1]; ++v) {
+    const int c = xl[v];
+    const int s0 = leaf_start[c], s1 = leaf_start[c + 1];
+    for (int j0 = s0; j0 < s1; j0 += kFmmThreads) {
+      const int n = min(kFmmThreads, s1 - j0);
+      __syncthreads();
+      if (tid < n)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) ss[q][tid] = srt[q * nn + j0 + tid];
+      __syncthreads();
+      if (tid < P * P)
+        for (int j = 0; j < n; ++j) dl_pair(xi, yi, ss[0][j], ss[1][j], ss[2][j], ss[3][j], ss[4][j], ax, ay);
+    }
+  }
+  if (tid < P * P) {
+    double *o = Lc + (int64_t)box * 2 * P * P;
+    o[tid] += ax;
+    o[P * P + tid] += ay;
+  }
+}
+
 // Children's locals += the parent's local interpolated to their grids,
 // boxes [b0, b0 + grid) of one level.
 template <int P>
@@ -286,20 +330,25 @@ __global__ __launch_bounds__(kFmmThreads) void fmm_l2l(int b0, const int *__rest
 }
 
 // One workgroup (one wave) per leaf: for each target of the leaf the local
-// expansion (when there is a far field) plus the direct sum over the
-// neighbouring leaves, written to part in node order.
+// expansion (leaves at level 2 or below), the direct sum over the touching
+// leaves (U list) and the multipoles of the W list (boxes smaller than the
+// leaf, well separated from it, whose parents touch it), written to part in
+// node order.  Boxes >= far0 carry local expansions.
 template <int P>
-__global__ __launch_bounds__(kLeafThreads) void fmm_leaf(int64_t nn, int leaf0, int far,
+__global__ __launch_bounds__(kLeafThreads) void fmm_leaf(int64_t nn, const int *__restrict__ leaf_box, int far0,
                                                          const int *__restrict__ leaf_start,
                                                          const int *__restrict__ ul_off, const int *__restrict__ ul,
+                                                         const int *__restrict__ wl_off, const int *__restrict__ wl,
                                                          const int *__restrict__ perm, const double *__restrict__ ctr,
                                                          const double *__restrict__ hb, const double *__restrict__ tm,
-                                                         const double *__restrict__ srt,
-                                                         const double *__restrict__ Lc, double *__restrict__ part) {
+                                                         const double *__restrict__ tn, const double *__restrict__ srt,
+                                                         const double *__restrict__ Q, const double *__restrict__ Lc,
+                                                         double *__restrict__ part) {
   __shared__ double stm[P * P];
   __shared__ double sl[2][P * P];
   __shared__ double ss[5][kLeafThreads];
-  const int leaf = blockIdx.x, box = leaf0 + leaf, tid = threadIdx.x;
+  const int leaf = blockIdx.x, box = leaf_box[leaf], tid = threadIdx.x;
+  const bool far = box >= far0;
   if (far)
     for (int e = tid; e < P * P; e += blockDim.x) {
       stm[e] = tm[e];
@@ -344,39 +393,32 @@ __global__ __launch_bounds__(kLeafThreads) void fmm_leaf(int64_t nn, int leaf0, 
           for (int j = 0; j < n; ++j) dl_pair(xi, yi, ss[0][j], ss[1][j], ss[2][j], ss[3][j], ss[4][j], ax, ay);
       }
     }
+    for (int u = wl_off[leaf]; u < wl_off[leaf + 1]; ++u) {
+      const int wb = wl[u];
+      const double wx = ctr[2 * wb], wy = ctr[2 * wb + 1], wh = hb[wb];
+      const double *q = Q + (int64_t)wb * 3 * P * P;
+      for (int b0 = 0; b0 < P * P; b0 += kLeafThreads) {
+        const int n = min(kLeafThreads, P * P - b0);
+        __syncthreads();
+        if (tid < n) {
+          const int b = b0 + tid;
+          ss[0][tid] = fma(wh, tn[b % P], wx);
+          ss[1][tid] = fma(wh, tn[b / P], wy);
+          ss[2][tid] = q[b];
+          ss[3][tid] = q[P * P + b];
+          ss[4][tid] = q[2 * P * P + b];
+        }
+        __syncthreads();
+        if (active)
+          for (int j = 0; j < n; ++j) dl_pair(xi, yi, ss[0][j], ss[1][j], ss[2][j], ss[3][j], ss[4][j], ax, ay);
+      }
+    }
     if (active) {
       const int i = perm[k];
       part[i] = ax;
       part[nn + i] = ay;
     }
   }
-}
-
-uint64_t morton(uint32_t ix, uint32_t iy) {
-  auto spread = [](uint64_t v) {
-    v &= 0xffffffffull;
-    v = (v | (v << 16)) & 0x0000ffff0000ffffull;
-    v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
-    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
-    v = (v | (v << 2)) & 0x3333333333333333ull;
-    v = (v | (v << 1)) & 0x5555555555555555ull;
-    return v;
-  };
-  return spread(ix) | (spread(iy) << 1);
-}
-
-void demorton(uint64_t c, uint32_t &ix, uint32_t &iy) {
-  auto pack = [](uint64_t v) {
-    v &= 0x5555555555555555ull;
-    v = (v | (v >> 1)) & 0x3333333333333333ull;
-    v = (v | (v >> 2)) & 0x0f0f0f0f0f0f0f0full;
-    v = (v | (v >> 4)) & 0x00ff00ff00ff00ffull;
-    v = (v | (v >> 8)) & 0x0000ffff0000ffffull;
-    v = (v | (v >> 16)) & 0x00000000ffffffffull;
-    return (uint32_t)v;
-  };
-  ix = pack(c);
-  iy = pack(c >> 1);
 }
 
 template <class T>
@@ -390,22 +432,25 @@ DevBuf<T> upload(const std::vector<T> &h, hipStream_t s) {
 
 struct FmmPlan : PairSum {
   sbie_geom g{};
-  int p = 0, depth = 0, nleaf = 0, nbox = 0;
+  int p = 0, depth = 0, nleaf = 0, nbox = 0, min_leaf_level = 0;
+  bool adaptive = false;
   int64_t nn = 0;
   std::vector<int> lev_off;   // boxes of level l: [lev_off[l], lev_off[l + 1])
-  DevBuf<int> perm, leaf_start, par, quad, child, vl_off, vl, ul_off, ul;
+  int nxbox = 0;              // boxes with a non-empty X list
+  DevBuf<int> perm, leaf_box, leaf_start, par, quad, child, vl_off, vl, ul_off, ul, wl_off, wl, xbox, xl_off, xl;
   DevBuf<double> ctr, hb, tm, tn, m2, Q, Lc, srt;
-  int64_t m2l_pairs = 0;      // box pairs in the interaction lists
-  int64_t p2p_pairs = 0;      // node pairs in the near field
+  int64_t m2l_pairs = 0;      // box pairs in the interaction (V) lists
+  int64_t m2p_pairs = 0;      // (leaf, box) pairs in the W lists
+  int64_t p2l_pairs = 0;      // (box, leaf) pairs in the X lists
+  int64_t p2p_pairs = 0;      // node pairs in the near field (U lists)
 
   template <int P>
   void run_p(const double *src, double *part, hipStream_t s) const {
     fmm_gather<<<ceil_div(nn, 256), 256, 0, s>>>(nn, perm.p, src, srt.p);
     SBIE_LAUNCH_CHECK();
-    const int leaf0 = lev_off[depth];
     const bool far = depth >= 2;
     if (far) {
-      fmm_p2m<P><<<nleaf, kFmmThreads, 0, s>>>(nn, leaf0, leaf_start.p, ctr.p, hb.p, tm.p, srt.p, Q.p);
+      fmm_p2m<P><<<nleaf, kFmmThreads, 0, s>>>(nn, leaf_box.p, leaf_start.p, ctr.p, hb.p, tm.p, srt.p, Q.p);
       SBIE_LAUNCH_CHECK();
       for (int l = depth - 1; l >= 2; --l) {
         const int nb = lev_off[l + 1] - lev_off[l];
@@ -416,6 +461,11 @@ struct FmmPlan : PairSum {
       const int nfar = lev_off[depth + 1] - lev_off[2];
       fmm_m2l<P><<<nfar, kFmmThreads, 0, s>>>(lev_off[2], vl_off.p, vl.p, ctr.p, hb.p, tn.p, Q.p, Lc.p);
       SBIE_LAUNCH_CHECK();
+      if (nxbox > 0) {
+        fmm_p2l<P><<<nxbox, kFmmThreads, 0, s>>>(nn, xbox.p, xl_off.p, xl.p, leaf_start.p, ctr.p, hb.p, tn.p, srt.p,
+                                                 Lc.p);
+        SBIE_LAUNCH_CHECK();
+      }
       for (int l = 3; l <= depth; ++l) {
         const int nb = lev_off[l + 1] - lev_off[l];
         if (nb == 0) continue;
@@ -423,8 +473,9 @@ struct FmmPlan : PairSum {
         SBIE_LAUNCH_CHECK();
       }
     }
-    fmm_leaf<P><<<nleaf, kLeafThreads, 0, s>>>(nn, leaf0, far ? 1 : 0, leaf_start.p, ul_off.p, ul.p, perm.p, ctr.p,
-                                               hb.p, tm.p, srt.p, Lc.p, part);
+    fmm_leaf<P><<<nleaf, kLeafThreads, 0, s>>>(nn, leaf_box.p, far ? lev_off[2] : nbox, leaf_start.p, ul_off.p, ul.p,
+                                               wl_off.p, wl.p, perm.p, ctr.p, hb.p, tm.p, tn.p, srt.p, Q.p, Lc.p,
+                                               part);
     SBIE_LAUNCH_CHECK();
   }
 
@@ -448,145 +499,24 @@ void FmmPlan::build(const sbie_geom *geom, const fmm_params *prm, hipStream_t s)
   g = *geom;
   nn = g.n_nodes;
   p = prm->cheb_n;
+  adaptive = prm->adaptive != 0;
+  const int target = prm->leaf_target > 0 ? prm->leaf_target : 64;
   // host copy of the node positions
   std::vector<double> hx(nn), hy(nn);
   SBIE_HIP(hipMemcpyAsync(hx.data(), g.x, nn * sizeof(double), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipMemcpyAsync(hy.data(), g.y, nn * sizeof(double), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipStreamSynchronize(s));
-  double x0 = hx[0], x1 = hx[0], y0 = hy[0], y1 = hy[0];
-  for (int64_t i = 0; i < nn; ++i) {
-    x0 = std::min(x0, hx[i]);
-    x1 = std::max(x1, hx[i]);
-    y0 = std::min(y0, hy[i]);
-    y1 = std::max(y1, hy[i]);
-  }
-  const double cx0 = 0.5 * (x0 + x1), cy0 = 0.5 * (y0 + y1);
-  double h0 = 0.5 * std::max(x1 - x0, y1 - y0);
-  h0 = h0 > 0.0 ? h0 * (1.0 + 1e-12) : 1.0;
-  auto codes_at = [&](int L, std::vector<uint64_t> &c) {
-    const double scale = (double)(1u << L) / (2.0 * h0);
-    const uint32_t top = (1u << L) - 1;
-    c.resize(nn);
-    for (int64_t i = 0; i < nn; ++i) {
-      const double fx = std::floor((hx[i] - (cx0 - h0)) * scale), fy = std::floor((hy[i] - (cy0 - h0)) * scale);
-      const uint32_t ix = (uint32_t)std::min<double>(top, std::max(0.0, fx));
-      const uint32_t iy = (uint32_t)std::min<double>(top, std::max(0.0, fy));
-      c[i] = morton(ix, iy);
-    }
-  };
-  std::vector<uint64_t> code;
-  if (prm->max_depth > 0) {
-    depth = prm->max_depth;
-    codes_at(depth, code);
-  } else {
-    // the shallowest depth whose non-empty leaves hold at most leaf_target
-    // nodes on average
-    const int target = prm->leaf_target > 0 ? prm->leaf_target : 64;
-    for (depth = 0;; ++depth) {
-      codes_at(depth, code);
-      std::vector<uint64_t> u(code);
-      std::sort(u.begin(), u.end());
-      const int64_t nl = std::unique(u.begin(), u.end()) - u.begin();
-      if (nn <= (int64_t)target * nl || depth == kMaxDepth) break;
-    }
-  }
-  // nodes in leaf order (stable, so a leaf keeps the node order of its curves)
-  std::vector<int> order(nn);
-  for (int64_t i = 0; i < nn; ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
-  // boxes per level, sorted codes; level L = depth holds the leaves
-  std::vector<std::vector<uint64_t>> lv(depth + 1);
-  std::vector<int> ls;   // leaf b holds the sorted nodes [ls[b], ls[b + 1])
-  {
-    std::vector<uint64_t> &leaves = lv[depth];
-    for (int64_t k = 0; k < nn; ++k) {
-      const uint64_t c = code[order[k]];
-      if (leaves.empty() || leaves.back() != c) {
-        leaves.push_back(c);
-        ls.push_back((int)k);
-      }
-    }
-    ls.push_back((int)nn);
-    nleaf = (int)leaves.size();
-    for (int l = depth - 1; l >= 0; --l) {
-      for (uint64_t c : lv[l + 1])
-        if (lv[l].empty() || lv[l].back() != (c >> 2)) lv[l].push_back(c >> 2);
-    }
-    leaf_start = upload(ls, s);
-  }
-  lev_off.assign(depth + 2, 0);
-  for (int l = 0; l <= depth; ++l) lev_off[l + 1] = lev_off[l] + (int)lv[l].size();
-  nbox = lev_off[depth + 1];
-  auto find = [&](int l, uint64_t c) -> int {
-    const auto &v = lv[l];
-    auto it = std::lower_bound(v.begin(), v.end(), c);
-    return (it != v.end() && *it == c) ? lev_off[l] + (int)(it - v.begin()) : -1;
-  };
-  std::vector<double> hctr(2 * (size_t)nbox), hhb(nbox);
-  std::vector<int> hpar(nbox, -1), hquad(nbox, 0), hchild(4 * (size_t)nbox, -1);
-  for (int l = 0; l <= depth; ++l) {
-    const double h = h0 / (double)(1u << l);
-    for (size_t b = 0; b < lv[l].size(); ++b) {
-      const int gb = lev_off[l] + (int)b;
-      uint32_t ix, iy;
-      demorton(lv[l][b], ix, iy);
-      hctr[2 * gb] = cx0 - h0 + (2.0 * ix + 1.0) * h;
-      hctr[2 * gb + 1] = cy0 - h0 + (2.0 * iy + 1.0) * h;
-      hhb[gb] = h;
-      if (l > 0) {
-        hpar[gb] = find(l - 1, lv[l][b] >> 2);
-        hquad[gb] = (int)(lv[l][b] & 3);
-        hchild[4 * (size_t)hpar[gb] + hquad[gb]] = gb;
-      }
-    }
-  }
-  // neighbours (same level, touching, itself included)
-  auto neighbours = [&](int l, uint64_t c, std::vector<int> &out) {
-    out.clear();
-    uint32_t ix, iy;
-    demorton(c, ix, iy);
-    const int64_t top = (int64_t)(1u << l) - 1;
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int64_t jx = (int64_t)ix + dx, jy = (int64_t)iy + dy;
-        if (jx < 0 || jy < 0 || jx > top || jy > top) continue;
-        const int f = find(l, morton((uint32_t)jx, (uint32_t)jy));
-        if (f >= 0) out.push_back(f);
-      }
-  };
-  std::vector<int> hvl_off(nbox + 1, 0), hvl, hul_off(nleaf + 1, 0), hul;
-  std::vector<int> nb_par, nb_self;
-  m2l_pairs = 0;
-  for (int l = 0; l <= depth; ++l)
-    for (size_t b = 0; b < lv[l].size(); ++b) {
-      const int gb = lev_off[l] + (int)b;
-      if (l >= 2) {
-        uint32_t ix, iy;
-        demorton(lv[l][b], ix, iy);
-        neighbours(l - 1, lv[l][b] >> 2, nb_par);
-        for (int pn : nb_par)
-          for (int q = 0; q < 4; ++q) {
-            const int c = hchild[4 * (size_t)pn + q];
-            if (c < 0) continue;
-            uint32_t jx, jy;
-            demorton(lv[l][c - lev_off[l]], jx, jy);
-            if (std::max(std::abs((int64_t)jx - ix), std::abs((int64_t)jy - iy)) > 1) hvl.push_back(c);
-          }
-      }
-      hvl_off[gb + 1] = (int)hvl.size();
-    }
-  m2l_pairs = (int64_t)hvl.size();
-  p2p_pairs = 0;
-  {
-    for (int b = 0; b < nleaf; ++b) {
-      neighbours(depth, lv[depth][b], nb_self);
-      for (int f : nb_self) {
-        hul.push_back(f - lev_off[depth]);
-        p2p_pairs += (int64_t)(ls[b + 1] - ls[b]) * (ls[f - lev_off[depth] + 1] - ls[f - lev_off[depth]]);
-      }
-      hul_off[b + 1] = (int)hul.size();
-    }
-  }
+  FmmTree t = build_fmm_tree(hx.data(), hy.data(), nn, target, prm->max_depth, adaptive);
+  depth = t.depth;
+  nleaf = t.nleaf;
+  nbox = t.nbox;
+  nxbox = t.nxbox;
+  min_leaf_level = t.min_leaf_level;
+  lev_off = t.lev_off;
+  m2l_pairs = t.m2l_pairs;
+  p2p_pairs = t.p2p_pairs;
+  m2p_pairs = t.m2p_pairs;
+  p2l_pairs = t.p2l_pairs;
   // Chebyshev tables
   std::vector<double> htn(p), htm((size_t)p * p), hm2(2 * (size_t)p * p);
   const long double pi = 3.141592653589793238462643383279502884L;
@@ -605,17 +535,23 @@ void FmmPlan::build(const sbie_geom *geom, const fmm_params *prm, hipStream_t s)
         for (int j = 1; j < p; ++j) acc += std::cos(j * std::acos(tk)) * std::cos(j * std::acos(sv));
         hm2[((size_t)q * p + K) * p + m] = (double)((1.0L + 2.0L * acc) / p);
       }
-  std::vector<int> hperm(order.begin(), order.end());
-  perm = upload(hperm, s);
-  par = upload(hpar, s);
-  quad = upload(hquad, s);
-  child = upload(hchild, s);
-  vl_off = upload(hvl_off, s);
-  vl = upload(hvl, s);
-  ul_off = upload(hul_off, s);
-  ul = upload(hul, s);
-  ctr = upload(hctr, s);
-  hb = upload(hhb, s);
+  perm = upload(t.order, s);
+  leaf_box = upload(t.leaf_box, s);
+  leaf_start = upload(t.leaf_start, s);
+  par = upload(t.par, s);
+  quad = upload(t.quad, s);
+  child = upload(t.child, s);
+  vl_off = upload(t.vl_off, s);
+  vl = upload(t.vl, s);
+  ul_off = upload(t.ul_off, s);
+  ul = upload(t.ul, s);
+  wl_off = upload(t.wl_off, s);
+  wl = upload(t.wl, s);
+  xbox = upload(t.xbox, s);
+  xl_off = upload(t.xl_off, s);
+  xl = upload(t.xl, s);
+  ctr = upload(t.ctr, s);
+  hb = upload(t.hb, s);
   tn = upload(htn, s);
   tm = upload(htm, s);
   m2 = upload(hm2, s);
@@ -645,11 +581,11 @@ extern "C" int fmm_plan(const sbie_geom *g, const fmm_params *p, sbie_fmm **out,
     if (!out || !p) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
     *out = nullptr;
     sbie::validate_geom(g);
-    if (p->reserved != 0) sbie::fail(SBIE_INVALID_ARGUMENT, "fmm_params.reserved must be 0");
+    if (p->adaptive != 0 && p->adaptive != 1) sbie::fail(SBIE_INVALID_ARGUMENT, "fmm_params.adaptive must be 0 or 1");
     if (p->cheb_n < 4 || p->cheb_n > 16 || (p->cheb_n & 1))
       sbie::fail(SBIE_INVALID_ARGUMENT, "cheb_n must be 4, 6, ..., 16 (got %d)", p->cheb_n);
-    if (p->max_depth < 0 || p->max_depth > sbie::kMaxDepth)
-      sbie::fail(SBIE_INVALID_ARGUMENT, "max_depth must be in [0, %d]", sbie::kMaxDepth);
+    if (p->max_depth < 0 || p->max_depth > sbie::kFmmMaxDepth)
+      sbie::fail(SBIE_INVALID_ARGUMENT, "max_depth must be in [0, %d]", sbie::kFmmMaxDepth);
     if (p->leaf_target < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "leaf_target must be >= 0");
     if (g->n_nodes >= ((int64_t)1 << 31)) sbie::fail(SBIE_UNSUPPORTED, "too many nodes");
     auto h = std::make_unique<sbie_fmm>();
@@ -685,9 +621,11 @@ extern "C" int fmm_get_stats(const sbie_fmm *f, fmm_stats *st) {
     st->depth = f->plan.depth;
     st->leaves = f->plan.nleaf;
     st->boxes = f->plan.nbox;
-    st->reserved = 0;
+    st->min_leaf_level = f->plan.min_leaf_level;
     st->m2l_box_pairs = f->plan.m2l_pairs;
     st->near_node_pairs = f->plan.p2p_pairs;
+    st->m2p_box_pairs = f->plan.m2p_pairs;
+    st->p2l_box_pairs = f->plan.p2l_pairs;
     return SBIE_OK;
   });
 }

@@ -5,6 +5,7 @@ workloads, using the CPU oracle only (``oracle/`` and the seeded inputs).
     python tests/golden/make_sigma.py pipe200    # n = 59,992: dense LU
     python tests/golden/make_sigma.py pipe1000   # n = 139,192: oracle FGMRES
     python tests/golden/make_sigma.py batch      # batch members with n <= 20,000: dense LU
+    python tests/golden/make_sigma.py refine pipe1000 300   # continue from a stored solution
 
 * pipe200 (seed 100, Poiseuille data): the completed double-layer matrix is
   assembled densely by the NumPy oracle (28.8 GB), factorised by LAPACK
@@ -21,6 +22,9 @@ workloads, using the CPU oracle only (``oracle/`` and the seeded inputs).
 
 * batch members (seeds 1000-1063 of the batched workload, Poiseuille data):
   those with at most 20,000 unknowns, by the dense LU of pipe200.
+* refine: the same FGMRES started from a stored solution (one more round of
+  restarts, i.e. iterative refinement with 80-bit residuals); of every
+  iterate whose true residual is evaluated the best one is kept.
 
 Each run writes ``sigma_<workload>_s<seed>.npy`` (FP64, no pickle) and a
 JSON record with the method, the final residual (80-bit evaluation), the
@@ -122,8 +126,56 @@ BATCH_SEEDS = range(1000, 1064)      # the 64 members of the batched workload
 BATCH_MAX_N = 20000                   # members solved by dense LU here
 
 
+def refine(work, seed, tol=1e-13, max_iter=600):
+    g = make_geometry(work, seed)
+    f = poiseuille_rhs(g)
+    base = os.path.join(HERE, f"sigma_{work}_s{seed}")
+    x0 = np.load(base + ".npy", allow_pickle=False)
+    with open(base + ".json") as fh:
+        meta = json.load(fh)
+    fn = np.linalg.norm(f)
+    r0 = float(np.linalg.norm(true_residual(g, f, x0)) / fn)
+    log(f"{work} seed {seed}: refining from true rel residual {r0:.3e}")
+    best = [r0, x0.copy()]
+
+    def resid(x):
+        r = true_residual(g, f, x)
+        rr = float(np.linalg.norm(r) / fn)
+        if rr < best[0]:
+            best[0], best[1] = rr, x.copy()
+        return r
+
+    t0 = time.perf_counter()
+    bd = solve.BlockDiagonal(g)
+    log(f"block-diagonal factor in {time.perf_counter() - t0:.0f}s")
+    last = [time.perf_counter()]
+
+    def progress(it, est):
+        if it % 25 == 0:
+            now = time.perf_counter()
+            log(f"iter {it}: estimate {est:.3e} ({(now - last[0]) / 25:.2f}s/iter)")
+            last[0] = now
+
+    res = solve.fgmres(lambda v: capply.apply(g, v), f, precond=bd, x0=x0, tol=tol, max_iter=max_iter,
+                       residual=resid, log=progress)
+    x = best[1]
+    r = true_residual(g, f, x)
+    meta.update(method=meta["method"] + "; then refined: the same FGMRES from the stored solution, "
+                "keeping the iterate of smallest 80-bit true residual",
+                refine_iters=int(res.iters), refine_start_residual=r0,
+                final_rel_residual_80bit=float(np.linalg.norm(r) / fn),
+                wall_s=meta.get("wall_s", 0.0) + time.perf_counter() - t0)
+    np.save(base + ".npy", x)
+    with open(base + ".json", "w") as fh:
+        json.dump(meta, fh, indent=1)
+    log(f"wrote {base}.npy: final rel residual {meta['final_rel_residual_80bit']:.3e}")
+
+
 def main():
     work = sys.argv[1] if len(sys.argv) > 1 else "pipe200"
+    if work == "refine":
+        refine(sys.argv[2], int(sys.argv[3]))
+        return
     if work == "batch":
         # every member of the batched workload small enough for a dense LU
         for sd in BATCH_SEEDS:

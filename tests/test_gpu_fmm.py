@@ -67,8 +67,9 @@ def test_shallow_tree_is_the_direct_sum(lib, tiny):
         assert rel_inf(y, a @ x) < 1e-13
 
 
+@pytest.mark.parametrize("adaptive", [False, True])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_error_falls_with_order(lib, medium, mode):
+def test_error_falls_with_order(lib, medium, mode, adaptive):
     """The full vector against the C oracle's operator (mode 0) and 600
     sampled double-layer-only rows (mode 1), Chebyshev orders 6 .. 16."""
     g, x, ref_full = medium
@@ -80,12 +81,16 @@ def test_error_falls_with_order(lib, medium, mode):
         ref = dlp.dlp_only_rows(g, x, rows)
     errs = {}
     for p in (6, 10, 14, 16):
-        f = lib.FMM(dg, cheb_n=p, leaf_target=48)
+        f = lib.FMM(dg, cheb_n=p, leaf_target=32 if adaptive else 48, adaptive=adaptive)
         st = f.stats()
         y = f.matvec(dg.vector(x), mode=mode).cpu().numpy()
         errs[p] = rel_inf(y[rows], ref)
-        print(f"cheb_n {p}: rel err {errs[p]:.2e}  {st}")
+        print(f"cheb_n {p} adaptive {adaptive}: rel err {errs[p]:.2e}  {st}")
         assert st["depth"] >= 4 and st["m2l_box_pairs"] > 0
+        if adaptive:
+            # leaves on several levels: the W and X lists are exercised
+            assert st["min_leaf_level"] < st["depth"]
+            assert st["m2p_box_pairs"] > 0 and st["p2l_box_pairs"] > 0
     # geometric decay, about a factor 4.5 per order (measured: 2.6e-5, 1.3e-7,
     # 3.2e-10, 1.2e-11 for the full product; the double-layer-only rows are
     # smaller, so relative to them the errors are ~6x larger)
@@ -97,16 +102,17 @@ def test_error_falls_with_order(lib, medium, mode):
     assert errs[16] < errs[14] < errs[10] < errs[6]
 
 
-def test_pipe200_full_vector(lib):
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_pipe200_full_vector(lib, adaptive):
     g = make_geometry("pipe200", 100)
     dg = lib.DeviceGeometry(g)
     x = random_vector(g.n_unknowns, 7)
     ref = capply.apply(g, x)
-    f = lib.FMM(dg, cheb_n=14)
+    f = lib.FMM(dg, cheb_n=14, adaptive=adaptive)
     print(f.stats())
     y = f.matvec(dg.vector(x)).cpu().numpy()
     err = rel_inf(y, ref)
-    print(f"pipe200 cheb_n 14: rel err {err:.2e}")
+    print(f"pipe200 cheb_n 14 adaptive {adaptive}: rel err {err:.2e}")
     assert err < 2e-9
 
 
@@ -154,7 +160,8 @@ def test_gmres_with_fmm_products_pipe200_golden(lib):
 def test_arguments_checked(lib, tiny):
     g, _ = tiny
     dg = lib.DeviceGeometry(g)
-    for bad in (dict(cheb_n=5), dict(cheb_n=18), dict(cheb_n=2), dict(max_depth=21), dict(leaf_target=-1)):
+    for bad in (dict(cheb_n=5), dict(cheb_n=18), dict(cheb_n=2), dict(max_depth=21), dict(leaf_target=-1),
+                dict(adaptive=2)):
         kw = dict(cheb_n=8)
         kw.update(bad)
         with pytest.raises(lib.SbieError) as e:
