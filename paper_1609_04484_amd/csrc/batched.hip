@@ -1,5 +1,8 @@
 // Variable-size batched dense kernels (double and float instantiations).
 #include <cstring>
+#include <exception>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "batched.hpp"
@@ -17,6 +20,33 @@ Stager::Stager(size_t bytes) : cap(bytes) {
 
 Stager::~Stager() {
   if (host) (void)hipHostFree(host);
+}
+
+namespace {
+std::mutex g_stager_mu;
+std::map<int, std::vector<Stager *>> g_stager_pool;   // idle rings per device, kept until exit
+}  // namespace
+
+StagerLease::StagerLease(size_t bytes, hipStream_t s) : s_(s) {
+  SBIE_HIP(hipGetDevice(&dev_));
+  {
+    std::lock_guard<std::mutex> lk(g_stager_mu);
+    auto &v = g_stager_pool[dev_];
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i]->cap >= bytes) {
+        st_ = v[i];
+        v.erase(v.begin() + (std::ptrdiff_t)i);
+        break;
+      }
+  }
+  if (!st_) st_ = new Stager(bytes);
+  st_->reset();
+}
+
+StagerLease::~StagerLease() {
+  if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s_);
+  std::lock_guard<std::mutex> lk(g_stager_mu);
+  g_stager_pool[dev_].push_back(st_);
 }
 
 OpFlops &op_flops() {

@@ -73,6 +73,27 @@ struct Stager {
   void reset() { used = 0; }
 };
 
+// A staging ring borrowed from a process-wide pool and returned when the
+// lease ends, so that repeated factorisations do not page-lock, map and free
+// tens of megabytes each time.  A lease that ends by an exception first
+// synchronises its stream (launches in flight may still read the rings); a
+// lease that ends normally must end after its stream has been synchronised.
+// The pool keeps one ring per concurrent user and device until the process
+// ends.
+class StagerLease {
+ public:
+  StagerLease(size_t bytes, hipStream_t s);
+  ~StagerLease();
+  StagerLease(const StagerLease &) = delete;
+  StagerLease &operator=(const StagerLease &) = delete;
+  Stager &operator*() { return *st_; }
+
+ private:
+  Stager *st_ = nullptr;
+  int dev_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
 // Algorithmic flop counts of the batched products and inverses issued by the
 // calling thread (GEMM 2 m n k; Gauss-Jordan inverse 2 n^3), the op log of
 // a factorisation.  Reset and read by its caller.

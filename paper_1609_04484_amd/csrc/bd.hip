@@ -39,7 +39,8 @@ void wall_inverse_tiles(double *M, int n, int nb, hipStream_t s) {
   StreamBuf<int32_t> info((size_t)npan, s);
   fill_value<double>(Z.p, (size_t)nb * nb, 0.0, s);
   fill_value<int>(reinterpret_cast<int *>(info.p), (size_t)npan, 0, s);
-  Stager st((size_t)4 << 20);
+  StagerLease lease((size_t)4 << 20, s);
+  Stager &st = *lease;
   for (int it = 0; it < npan; ++it) {
     const int p0 = it * nb, pb = std::min(nb, n - p0);
     double *Mpp = M + p0 + (size_t)p0 * n;
@@ -192,7 +193,8 @@ void bd_build_slp(const sbie_geom *g, sbie_bd *bd, hipStream_t s) {
     bd->wmat.alloc((size_t)bd->nwall * bd->nwall);
     slp_assemble(g, bd->widx.p, bd->nwall, bd->widx.p, bd->nwall, bd->wmat.p, bd->nwall, s);
     {
-      Stager st((size_t)48 << 20);
+      StagerLease lease((size_t)48 << 20, s);
+      Stager &st = *lease;
       DevBuf<int32_t> winfo(1);
       inverse_batched_blocked<double>({bd->wmat.p}, {(int)bd->nwall}, winfo.p, st, s);
       int32_t hw = 0;

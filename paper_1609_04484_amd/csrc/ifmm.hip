@@ -808,7 +808,8 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     if (rad[k] >= leaf_h)
       fail(SBIE_UNSUPPORTED, "pore %d radius %.3g exceeds the leaf box side %.3g", k, rad[k], leaf_h);
 
-  Stager st((size_t)64 << 20);
+  StagerLease lease((size_t)64 << 20, s);
+  Stager &st = *lease;
   ChunkCache chunk_cache;   // declared before every temporary arena: outlives them
   DevBuf<double> wl(1);
   wall_length(g, wl.p, s);
