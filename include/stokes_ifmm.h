@@ -186,6 +186,10 @@ int stokes_velocity(const sbie_geom *g, const double *sigma, const double *px, c
  * targets_per_thread in {1, 2, 4, 8}; source_chunks >= 1 splits the source
  * loop across that many workgroups per target tile (0 = automatic). */
 int stokes_dlp_matvec_set_shape(int targets_per_thread, int source_chunks);
+/* Schedule of the batched products' pair stage (stokes_dlp_matvec_batched,
+ * gmres_solve_batched): 1 = persistent grid with a device work queue (the
+ * default), 0 = one workgroup per item.  Both give identical results. */
+int stokes_dlp_matvec_batched_set_schedule(int persistent);
 
 /* Kernel timing of the matvec's pair kernel (the dominant kernel): while
  * enabled, every launch of it is bracketed by HIP events recorded on the
@@ -414,7 +418,10 @@ int stokes_slp_velocity(const sbie_geom *g, const double *sigma, const double *p
  * ------------------------------------------------------------------------ */
 /* y_b = A_b x_b for every member b (geoms: host array of `count`
  * descriptors; x, y: host arrays of device pointers).  Every stage of the
- * product is one launch for the whole batch; same modes and results as
+ * product is one launch for the whole batch; the pair stage is by default a
+ * persistent grid (as many workgroups as the device holds at once) whose
+ * workgroups draw (member, target tile, source chunk) items from a device
+ * work queue until it is empty.  Same modes and results as
  * stokes_dlp_matvec with the same launch shape.  Synchronises the stream. */
 int stokes_dlp_matvec_batched(const sbie_geom *geoms, int32_t count, const double *const *x,
                               double *const *y, int mode, void *stream);

@@ -152,6 +152,7 @@ EXPORTS = {
     "fmm_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(FmmStats)]),
     "fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "stokes_dlp_matvec_batched_set_schedule": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "bd_factor": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(ctypes.c_void_p), _c_dp]),
@@ -309,6 +310,12 @@ def velocity(dg: DeviceGeometry, sigma: torch.Tensor, px: torch.Tensor, py: torc
 
 def set_matvec_shape(targets_per_thread: int, source_chunks: int = 0):
     check(load().stokes_dlp_matvec_set_shape(targets_per_thread, source_chunks))
+
+
+def set_batched_schedule(persistent: bool):
+    """Pair stage of the batched products: persistent work-queue grid (True,
+    the default) or one workgroup per item (False)."""
+    check(load().stokes_dlp_matvec_batched_set_schedule(int(persistent)))
 
 
 def kernel_timing(enable: bool):

@@ -63,9 +63,13 @@ def main(argv=None):
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=100)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--autotune", default=None, help="JSON cache path: tune the matvec shape")
+    ap.add_argument("--schedule", default="queue", choices=["queue", "grid"],
+                    help="pair stage of the batched products: persistent work-queue grid or "
+                         "one workgroup per item")
     a = ap.parse_args(argv)
+    L.set_batched_schedule(a.schedule == "queue")
     log = lambda m: print(m, file=sys.stderr, flush=True)
     geoms, dgs, fs = make_batch(a.members, a.seed)
     ns = [g.n_unknowns for g in geoms]
@@ -88,6 +92,7 @@ def main(argv=None):
     print(json.dumps(dict(
         members=a.members, n_min=min(ns), n_max=max(ns), n_total=sum(ns),
         eps=a.eps, cheb_n=a.cheb_n, precision=a.precision, tol=a.tol, workers=a.workers,
+        schedule=a.schedule,
         matvec_shape=shape,
         sequential_s=t_seq, batched_s=t_bat, batched_factor_s=t_fac,
         solves_per_s_sequential=a.members / t_seq, solves_per_s_batched=a.members / t_bat,

@@ -184,6 +184,7 @@ struct BatchMatvec {
   DevBuf<char> desc;
   char *hdesc = nullptr;
   hipEvent_t staged = nullptr;   // the last table upload has been consumed
+  DevBuf<unsigned long long> queue;   // work counter of the persistent pair stage
   size_t desc_cap = 0;
   int tpt = 4;
   BatchMatvec(const sbie_geom *const *g, int count);

@@ -34,6 +34,7 @@ constexpr int kPoreChunk = 64;
 
 int g_tpt = 4;        // targets per thread
 int g_chunks = 0;     // source chunks (0 = automatic)
+int g_batch_queue = 1;   // batched pair stage: persistent work queue (1) or one workgroup per item (0)
 
 // optional event bracketing of the pair kernel
 bool g_timing = false;
@@ -272,31 +273,34 @@ __device__ __forceinline__ void dlp_pairs_body(const double *__restrict__ src, c
     }
   }
   __syncthreads();
-  if (wv != 0) return;
+  // wave 0 adds the other waves' sums and writes (no early exit for the
+  // other waves: the persistent batch kernel runs this body in a loop)
+  if (wv == 0) {
 #pragma unroll
-  for (int o = 0; o < kWaves - 1; ++o)
+    for (int o = 0; o < kWaves - 1; ++o)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (ACC) {
+          two_sum_acc(ax[t], cxa[t], red[o][NV * t][lane]);
+          two_sum_acc(ay[t], cya[t], red[o][NV * t + 1][lane]);
+          cxa[t] += red[o][NV * t + 2][lane];
+          cya[t] += red[o][NV * t + 3][lane];
+        } else {
+          ax[t] += red[o][NV * t][lane];
+          ay[t] += red[o][NV * t + 1][lane];
+        }
+      }
+    double *px = part + ch * NV * nt;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      if (ACC) {
-        two_sum_acc(ax[t], cxa[t], red[o][NV * t][lane]);
-        two_sum_acc(ay[t], cya[t], red[o][NV * t + 1][lane]);
-        cxa[t] += red[o][NV * t + 2][lane];
-        cya[t] += red[o][NV * t + 3][lane];
-      } else {
-        ax[t] += red[o][NV * t][lane];
-        ay[t] += red[o][NV * t + 1][lane];
-      }
-    }
-  double *px = part + ch * NV * nt;
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int64_t i = tile0 + (int64_t)t * kTileLanes;
-    if (i < nt) {
-      px[i] = ax[t];
-      px[nt + i] = ay[t];
-      if (ACC) {
-        px[2 * nt + i] = cxa[t];
-        px[3 * nt + i] = cya[t];
+      const int64_t i = tile0 + (int64_t)t * kTileLanes;
+      if (i < nt) {
+        px[i] = ax[t];
+        px[nt + i] = ay[t];
+        if (ACC) {
+          px[2 * nt + i] = cxa[t];
+          px[3 * nt + i] = cya[t];
+        }
       }
     }
   }
@@ -774,6 +778,34 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs_b(const BMember *__restrict_
   dlp_pairs_body<T, ACC>(M.src, M.x, M.y, M.nn, M.nn, M.chunk, M.part, u % M.tiles, u / M.tiles);
 }
 
+// The same work items as dlp_pairs_b (every (member, tile, chunk) of the
+// batch) taken from a device work queue by a persistent grid sized to the
+// device's resident workgroups: each workgroup draws the next item index
+// with one atomic add until the queue is exhausted, so members of any size
+// mix freely and no workgroup waits on another.  Results are identical to
+// dlp_pairs_b (the same body on the same items).
+template <int T, bool ACC>
+__global__ __launch_bounds__(kBlock) void dlp_pairs_bq(const BMember *__restrict__ d,
+                                                       const int64_t *__restrict__ st, int nb,
+                                                       unsigned long long *queue, int64_t total) {
+  __shared__ int64_t item;
+  for (;;) {
+    // the barrier also orders the previous item's LDS reduction before the
+    // next item's writes to it
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t u0 = item;
+    __syncthreads();
+    if (u0 >= total) return;   // uniform over the workgroup
+    const int b = find_member(st, nb, u0);
+    const BMember &M = d[b];
+    const int64_t u = u0 - st[b];
+    dlp_pairs_body<T, ACC>(M.src, M.x, M.y, M.nn, M.nn, M.chunk, M.part, u % M.tiles, u / M.tiles);
+  }
+}
+
+__global__ void reset_queue(unsigned long long *queue) { *queue = 0ull; }
+
 template <bool ACC>
 __global__ __launch_bounds__(kBlock) void completion_b(const BMember *__restrict__ d,
                                                        const int64_t *__restrict__ st, int nb) {
@@ -819,6 +851,7 @@ BatchMatvec::BatchMatvec(const sbie_geom *const *g, int count) {
   desc.alloc(desc_cap);
   SBIE_HIP(hipHostMalloc((void **)&hdesc, desc_cap, hipHostMallocDefault));
   SBIE_HIP(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+  queue.alloc(1);
 }
 
 BatchMatvec::~BatchMatvec() {
@@ -888,7 +921,25 @@ void BatchMatvec::run(const std::vector<int> &members, const std::vector<const d
     wall_flux_b<<<nb, 1024, 0, s>>>(dd);
     SBIE_LAUNCH_CHECK();
   }
-  if (acc) {
+  if (g_batch_queue && acc_st[kStPair] > 0) {
+    // persistent grid: as many workgroups as the device holds at once (the
+    // occupancy of the plain kernel with this shape), at most one per item
+    const int64_t items = acc_st[kStPair];
+    const unsigned pg = (unsigned)std::min<int64_t>(items, resident_pair_blocks(T));
+    reset_queue<<<1, 1, 0, s>>>(queue.p);
+    SBIE_LAUNCH_CHECK();
+    if (acc) {
+      dlp_pairs_bq<1, true><<<pg, kBlock, 0, s>>>(dd, stt(kStPair), nb, queue.p, items);
+    } else {
+      switch (T) {
+        case 1: dlp_pairs_bq<1, false><<<pg, kBlock, 0, s>>>(dd, stt(kStPair), nb, queue.p, items); break;
+        case 2: dlp_pairs_bq<2, false><<<pg, kBlock, 0, s>>>(dd, stt(kStPair), nb, queue.p, items); break;
+        case 4: dlp_pairs_bq<4, false><<<pg, kBlock, 0, s>>>(dd, stt(kStPair), nb, queue.p, items); break;
+        case 8: dlp_pairs_bq<8, false><<<pg, kBlock, 0, s>>>(dd, stt(kStPair), nb, queue.p, items); break;
+        default: fail(SBIE_INVALID_ARGUMENT, "targets per thread must be 1, 2, 4 or 8");
+      }
+    }
+  } else if (acc) {
     dlp_pairs_b<1, true><<<grid(kStPair), kBlock, 0, s>>>(dd, stt(kStPair), nb);
   } else {
     switch (T) {
@@ -1058,6 +1109,14 @@ extern "C" int stokes_dlp_matvec_set_shape(int targets_per_thread,
     if (source_chunks < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "source_chunks < 0");
     sbie::g_tpt = targets_per_thread;
     sbie::g_chunks = source_chunks;
+    return SBIE_OK;
+  });
+}
+
+extern "C" int stokes_dlp_matvec_batched_set_schedule(int persistent) {
+  return sbie::guarded([&]() {
+    if (persistent != 0 && persistent != 1) sbie::fail(SBIE_INVALID_ARGUMENT, "persistent must be 0 or 1");
+    sbie::g_batch_queue = persistent;
     return SBIE_OK;
   });
 }

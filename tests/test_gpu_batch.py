@@ -44,8 +44,17 @@ def members():
             make_geometry(dict(SMALL, n_pores=7, n_int=40), 8)]
 
 
+@pytest.fixture(params=[True, False], ids=["work_queue", "one_per_item"])
+def schedule(lib, request):
+    """The batched pair stage as a persistent grid drawing items from a device
+    work queue (the default) and as one workgroup per item."""
+    lib.set_batched_schedule(request.param)
+    yield request.param
+    lib.set_batched_schedule(True)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_matvec_batched_equals_single(lib, mode):
+def test_matvec_batched_equals_single(lib, mode, schedule):
     gs = members()
     dgs = [lib.DeviceGeometry(g) for g in gs]
     xs = [dg.vector(random_vector(g.n_unknowns, 10 + b)) for b, (g, dg) in enumerate(zip(gs, dgs))]
@@ -65,8 +74,9 @@ def test_matvec_batched_matches_oracle(lib):
         assert np.abs(y.cpu().numpy() - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-def test_matvec_batched_many_members(lib):
-    """More members than one wave of the member search, uneven sizes."""
+def test_matvec_batched_many_members(lib, schedule):
+    """More members than one wave of the member search, uneven sizes; with
+    the work queue, more items than the persistent grid has workgroups."""
     gs = [make_geometry(dict(SMALL, n_pores=3 + (b % 5), length=2.0 + 0.1 * b), 30 + b)
           for b in range(70)]
     dgs = [lib.DeviceGeometry(g) for g in gs]
