@@ -26,13 +26,14 @@ METRIC = ("GMRES solves/s to rel. residual 1e-10 at N≈128k: IFMM vs block-diag
 FP64_VECTOR_PEAK = 78.6e12     # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 PAIR_FLOPS = 19                # algorithmic flops per node pair of the matvec
 
-# HBM bytes per launch of the pair kernel at the default workload, from two
+# HBM bytes per launch of the timed pair stage at the default workload (the
+# symmetric pair kernel and the reduction of its partial sums), from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors
-# read off a plain 1 GiB device copy; profiles/dlp_pairs_pipe1000_hbm_counters.md).
+# read off a plain 1 GiB device copy; profiles/dlp_pairs_sym_pipe1000_counters.md).
 # Valid only for the kernel source they were taken with: reported as null
 # once matvec.hip changes.
-PAIR_TRAFFIC = {"matvec_sha256": "12684c5fadcb042194e474f27ecf6d39a9197d8befabfdcb11ac51cf85fc0cae", "bytes_per_launch": 43654144,
-                "workload": "pipe1000"}
+PAIR_TRAFFIC = {"matvec_sha256": "478043651d955700d0281a9898e39890c0bdaff352d2793a1ee0c66497788162",
+                "bytes_per_launch": 280056218, "workload": "pipe1000"}
 
 
 def pair_traffic(workload):
@@ -440,7 +441,10 @@ def main():
     # dominant kernel: the matvec pair kernel (FP64 vector ALU bound)
     kernel_ms = hr["pair_kernel_ms"]
     achieved = PAIR_FLOPS * float(nn) ** 2 / (kernel_ms * 1e-3)
-    roofline = {"bound": "alu", "kernel": "dlp_pairs", "achieved": achieved / 1e12,
+    plan = lib.matvec_plan(dg)
+    roofline = {"bound": "alu",
+                "kernel": "dlp_pairs_sym + sym_reduce" if plan["symmetric"] else "dlp_pairs",
+                "achieved": achieved / 1e12,
                 "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK, "traffic": pair_traffic(args.workload),
                 "traffic_unit": "HBM bytes per launch", "avg_kernel_ms": kernel_ms}

@@ -186,6 +186,21 @@ int stokes_velocity(const sbie_geom *g, const double *sigma, const double *px, c
  * targets_per_thread in {1, 2, 4, 8}; source_chunks >= 1 splits the source
  * loop across that many workgroups per target tile (0 = automatic). */
 int stokes_dlp_matvec_set_shape(int targets_per_thread, int source_chunks);
+/* Symmetric evaluation of the plain products' pair sum: the contributions of
+ * node j to node i and of node i to node j share r, rho^2 and 1/rho^4, so
+ * every unordered pair of nodes is evaluated once for both (superblocks of
+ * 4 x 4 tiles of 256 nodes; per-superblock partial sums added in a fixed
+ * order, so the result does not depend on the schedule).  mode 0 = never;
+ * 1 = from 16,384 nodes up to 131,072 nodes (the default; its partial sums
+ * take about nn^2 / 64 bytes); 2 = always up to 131,072 nodes.  Compensated
+ * products and an explicit source-chunk count always use the chunked pair
+ * kernel. */
+int stokes_dlp_matvec_set_symmetric(int mode);
+/* The launch plan stokes_dlp_matvec would use for this geometry and mode
+ * (host outputs): symmetric evaluation (1) or chunked kernel (0), source
+ * chunks (1 for the symmetric evaluation), targets per thread. */
+int stokes_dlp_matvec_describe_plan(const sbie_geom *g, int mode, int32_t *symmetric, int32_t *chunks,
+                                    int32_t *targets_per_thread);
 /* Schedule of the batched products' pair stage (stokes_dlp_matvec_batched,
  * gmres_solve_batched): 1 = persistent grid with a device work queue (the
  * default), 0 = one workgroup per item.  Both give identical results. */

@@ -153,6 +153,11 @@ EXPORTS = {
     "fmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "stokes_dlp_matvec_set_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "stokes_dlp_matvec_batched_set_schedule": (ctypes.c_int, [ctypes.c_int]),
+    "stokes_dlp_matvec_set_symmetric": (ctypes.c_int, [ctypes.c_int]),
+    "stokes_dlp_matvec_describe_plan": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.c_int,
+                                                       ctypes.POINTER(ctypes.c_int32),
+                                                       ctypes.POINTER(ctypes.c_int32),
+                                                       ctypes.POINTER(ctypes.c_int32)]),
     "sbie_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "sbie_kernel_time": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "bd_factor": (ctypes.c_int, [ctypes.POINTER(SbieGeom), ctypes.POINTER(ctypes.c_void_p), _c_dp]),
@@ -310,6 +315,20 @@ def velocity(dg: DeviceGeometry, sigma: torch.Tensor, px: torch.Tensor, py: torc
 
 def set_matvec_shape(targets_per_thread: int, source_chunks: int = 0):
     check(load().stokes_dlp_matvec_set_shape(targets_per_thread, source_chunks))
+
+
+def set_matvec_symmetric(mode: int):
+    """Symmetric pair evaluation of the plain products: 0 never, 1 where it
+    pays (the default), 2 always (up to 131,072 nodes)."""
+    check(load().stokes_dlp_matvec_set_symmetric(int(mode)))
+
+
+def matvec_plan(dg: DeviceGeometry, mode: int = 0) -> dict:
+    """The launch plan of stokes_dlp_matvec for this geometry and mode."""
+    sym, ch, tpt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(load().stokes_dlp_matvec_describe_plan(ctypes.byref(dg.c), mode, ctypes.byref(sym),
+                                                 ctypes.byref(ch), ctypes.byref(tpt)))
+    return {"symmetric": bool(sym.value), "chunks": ch.value, "targets_per_thread": tpt.value}
 
 
 def set_batched_schedule(persistent: bool):

@@ -141,11 +141,16 @@ struct MatvecWork {
   int chunks = 0;            // source chunks of the pair kernel
   int pchunks = 0;           // pore chunks of the completion kernel
   int tpt = 4;               // targets per thread
+  int sym = 0;               // symmetric pair evaluation (plain modes)
+  int sym_R = 0;             // superblocks per side of the symmetric evaluation
+  double *sym_buf = nullptr; // its partial sums
   size_t doubles() const;
 };
 
 // Plan the launch shape and the scratch size (in doubles) for a geometry.
-MatvecWork plan_matvec(const sbie_geom *g);
+// allow_sym: the plain modes may use the symmetric pair evaluation (one
+// partial sum; the compensated mode needs a plan without it).
+MatvecWork plan_matvec(const sbie_geom *g, bool allow_sym = true);
 size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g);
 void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base);
 // An alternative evaluation of the double-layer pair sum (the fast multipole

@@ -606,7 +606,7 @@ extern "C" int stokes_dlp_matvec_fmm(const sbie_fmm *f, const double *x, double 
     const int64_t n = sbie::n_unknowns(g);
     if (x < y + n && y < x + n) sbie::fail(SBIE_INVALID_ARGUMENT, "x and y overlap");
     hipStream_t s = (hipStream_t)stream;
-    sbie::MatvecWork w = sbie::plan_matvec(g);
+    sbie::MatvecWork w = sbie::plan_matvec(g, false);
     w.chunks = 1;
     sbie::StreamBuf<double> scratch(sbie::matvec_scratch_doubles(w, g), s);
     sbie::bind_matvec_scratch(w, g, scratch.p);

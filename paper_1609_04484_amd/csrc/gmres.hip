@@ -338,21 +338,29 @@ int gmres_run_op(const KrylovOp &op, const double *f, double *x,
 
 int gmres_run(const sbie_geom *g, const double *f, double *x,
               const gmres_params *p, gmres_result *res, hipStream_t s) {
-  MatvecWork mw = plan_matvec(g);
+  // plain products (Arnoldi) may use the symmetric pair evaluation; the
+  // compensated products (true residuals) use the chunked kernel
+  const PairSum *fmm = p->fmm ? fmm_pair_sum(p->fmm) : nullptr;
+  MatvecWork mw = plan_matvec(g, !fmm);
   DevBuf<double> mvs(matvec_scratch_doubles(mw, g));
   bind_matvec_scratch(mw, g, mvs.p);
+  MatvecWork ma = plan_matvec(g, false);
+  DevBuf<double> mas(mw.sym ? matvec_scratch_doubles(ma, g) : 0);
+  if (mw.sym) bind_matvec_scratch(ma, g, mas.p);
+  MatvecWork &macc = mw.sym ? ma : mw;
   // with a fast-multipole plan: its pair sum in the Arnoldi products (one
   // partial sum), the direct compensated product for true residuals
-  const PairSum *fmm = p->fmm ? fmm_pair_sum(p->fmm) : nullptr;
-  MatvecWork mf = plan_matvec(g);
+  MatvecWork mf = plan_matvec(g, false);
   mf.chunks = 1;
   DevBuf<double> mfs(fmm ? matvec_scratch_doubles(mf, g) : 0);
   if (fmm) bind_matvec_scratch(mf, g, mfs.p);
   KrylovOp op{n_unknowns(g), [&](const double *in, double *out, bool accurate, hipStream_t st) {
-                if (fmm && !accurate)
+                if (accurate)
+                  matvec_run(g, in, out, SBIE_MV_FULL_ACCURATE, macc, st);
+                else if (fmm)
                   matvec_run(g, in, out, SBIE_MV_FULL, mf, st, fmm);
                 else
-                  matvec_run(g, in, out, accurate ? SBIE_MV_FULL_ACCURATE : SBIE_MV_FULL, mw, st);
+                  matvec_run(g, in, out, SBIE_MV_FULL, mw, st);
               }};
   return gmres_run_op(op, f, x, p, res, s);
 }

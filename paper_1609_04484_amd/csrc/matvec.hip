@@ -35,6 +35,7 @@ constexpr int kPoreChunk = 64;
 int g_tpt = 4;        // targets per thread
 int g_chunks = 0;     // source chunks (0 = automatic)
 int g_batch_queue = 1;   // batched pair stage: persistent work queue (1) or one workgroup per item (0)
+int g_sym_mode = 1;      // symmetric pair evaluation: 0 never, 1 where it pays, 2 always (plain modes)
 
 // optional event bracketing of the pair kernel
 bool g_timing = false;
@@ -327,6 +328,225 @@ __global__ __launch_bounds__(kBlock) void dlp_pairs(
   dlp_pairs_body<T, ACC>(src, xs, ys, nt, nn, chunk, part, tile, ch);
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric evaluation of the pair sum.  The contributions of node j to node
+// i and of node i to node j share r = x_i - x_j (up to its sign), rho^2 and
+// 1/rho^4: for q_i, q_j the records' tensors,
+//   to i:  r (r^T q_j r) / rho^4,      to j:  -r (r^T q_i r) / rho^4,
+// so one evaluation of the shared part serves both, and every unordered
+// pair of distinct tiles is visited once.  Work unit: a superblock pair
+// (Kr <= Kc) of SB x SB tiles of 256 nodes.  Each lane owns 4 targets of the
+// current row tile and one node of its wave's quarter of the column tile;
+// the column nodes are passed round the wave by DPP rotations (one lane per
+// step, 64 steps), each carrying its own sum, so no cross-lane reduction is
+// needed: the row tile's sums stay in registers, the column nodes' sums go
+// to LDS (one slot per node) until the superblock is done.  Diagonal tiles (I = J) are
+// summed one way only, the self pair included (zero as in dlp_pairs).
+// Partial sums: for the targets of superblock K, R + 1 slots of 2 x SB x 256
+// doubles, slot Kc - K for the row part of superblock pair (K, Kc) and slot
+// R - K + Kr for the column part of (Kr, K); every slot is written once per
+// product, then sym_reduce adds each target's slots in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kSymT = 4;                          // targets per lane
+constexpr int kSymTile = kTileLanes * kSymT;      // 256 nodes per tile
+constexpr int kSymSB = 4;                         // tiles per superblock side
+constexpr int kSymSBN = kSymSB * kSymTile;        // nodes per superblock
+
+// The value of the previous lane (lane l receives lane l - 1, lane 0 lane
+// 63): a DPP whole-wave rotation (wave_ror:1), two VALU moves per double
+// and no trip through LDS.  (Measured at the 1000-pore pipe: 1.82 ms per
+// product against 1.98 ms when the ring goes through the LDS crossbar.)
+__device__ __forceinline__ double ring_next(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x13C, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, 0x13C, 0xF, 0xF, false));
+}
+
+// This lane's T targets (positions xi, yi; tensors qa = q_xx, qb = q_xy +
+// q_yx, qc = q_yy) against the node this lane currently holds (position xj,
+// yj, tensor ja, jb, jc): the targets' sums into ax, ay, the node's sum
+// (before its sign) into bx, by.  One batched reciprocal for the T pairs.
+template <int T>
+__device__ __forceinline__ void sym_pairs(const double *xi, const double *yi, const double *qa, const double *qb,
+                                          const double *qc, double xj, double yj, double ja, double jb, double jc,
+                                          double *ax, double *ay, double &bx, double &by) {
+  double rx[T], ry[T], ryy[T], r2[T], inv[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    rx[t] = xi[t] - xj;
+    ry[t] = yi[t] - yj;
+    ryy[t] = fma(ry[t], ry[t], 1e-100);
+    r2[t] = fma(rx[t], rx[t], ryy[t]);
+  }
+  batch_recip<T>(r2, inv);
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const double i2 = inv[t] * inv[t];
+    const double h = fma(jb, ry[t], ja * rx[t]);
+    const double c = fma(h, rx[t], jc * ryy[t]) * i2;
+    ax[t] = fma(c, rx[t], ax[t]);
+    ay[t] = fma(c, ry[t], ay[t]);
+    const double h2 = fma(qb[t], ry[t], qa[t] * rx[t]);
+    const double c2 = fma(h2, rx[t], qc[t] * ryy[t]) * i2;
+    bx = fma(c2, rx[t], bx);
+    by = fma(c2, ry[t], by);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void dlp_pairs_sym(const double *__restrict__ src,
+                                                        const double *__restrict__ xs,
+                                                        const double *__restrict__ ys, int64_t nn, int ntiles,
+                                                        int R, double *__restrict__ P) {
+  constexpr int T = kSymT;
+  // superblock pair of this workgroup, row-major over the upper triangle:
+  // row k starts at k R - k (k - 1) / 2
+  const int64_t b = blockIdx.x;
+  auto start = [&](int64_t k) { return k * R - k * (k - 1) / 2; };
+  const double tr = 2.0 * R + 1.0;
+  int Kr = (int)floor(0.5 * (tr - sqrt(fmax(0.0, tr * tr - 8.0 * (double)b))));
+  Kr = Kr < 0 ? 0 : (Kr > R - 1 ? R - 1 : Kr);
+  while (Kr > 0 && start(Kr) > b) --Kr;
+  while (Kr + 1 < R && start(Kr + 1) <= b) ++Kr;
+  const int Kc = Kr + (int)(b - start(Kr));
+  Kr = __builtin_amdgcn_readfirstlane(Kr);
+  const int Kcu = __builtin_amdgcn_readfirstlane(Kc);
+
+  __shared__ double rev[kSymSB][2][kSymTile];
+  __shared__ double red[kWaves - 1][2 * T][kTileLanes];
+  for (int e = threadIdx.x; e < kSymSB * 2 * kSymTile; e += blockDim.x) (&rev[0][0][0])[e] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t slot_doubles = 2 * (int64_t)kSymSBN;
+  for (int ti = 0; ti < kSymSB; ++ti) {
+    const int I = Kr * kSymSB + ti;
+    if (I >= ntiles) break;
+    double xi[T], yi[T], qa[T], qb[T], qc[T], ax[T], ay[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int64_t i = (int64_t)I * kSymTile + lane + (int64_t)t * kTileLanes;
+      if (i < nn) {
+        xi[t] = xs[i];
+        yi[t] = ys[i];
+        qa[t] = src[8 * i + 2];
+        qb[t] = src[8 * i + 3];
+        qc[t] = src[8 * i + 4];
+      } else {
+        // padding targets: far from every node, at distinct places, no
+        // tensor (their column contributions vanish)
+        xi[t] = xs[nn - 1] + 1.0e3 * (double)(t + 1);
+        yi[t] = ys[nn - 1];
+        qa[t] = qb[t] = qc[t] = 0.0;
+      }
+      ax[t] = 0.0;
+      ay[t] = 0.0;
+    }
+    const int tj0 = (Kr == Kcu) ? ti : 0;
+    for (int tj = tj0; tj < kSymSB; ++tj) {
+      const int J = Kcu * kSymSB + tj;
+      if (J >= ntiles) break;
+      const int64_t jb = (int64_t)J * kSymTile;
+      // this wave's quarter of tile J: 16 T consecutive nodes
+      constexpr int kQuarter = kSymTile / kWaves;
+      const int64_t q0 = jb + (int64_t)wv * kQuarter;
+      if (J == I) {
+        const int j0 = (int)q0;
+        const int j1 = (int)(q0 + kQuarter < nn ? q0 + kQuarter : nn);
+        double cxa[T], cya[T];
+        int j = j0;
+        for (; j + 1 < j1; j += 2) pair_step<T, 2, false>(src, j, xi, yi, ax, ay, cxa, cya);
+        for (; j < j1; ++j) pair_step<T, 1, false>(src, j, xi, yi, ax, ay, cxa, cya);
+      } else {
+        // the quarter in rings of 64 nodes, one per lane, each passed round
+        // the wave one lane per step: after 64 steps every lane has met
+        // every node of the ring and each node (with its sum) is back in
+        // its own lane
+        for (int sub = 0; sub < kQuarter / kTileLanes; ++sub) {
+          const int jl = wv * kQuarter + sub * kTileLanes + lane;
+          const int64_t jn = jb + jl;
+          double xj, yj, ja, jbq, jc;
+          if (jn < nn) {
+            xj = xs[jn];
+            yj = ys[jn];
+            ja = src[8 * jn + 2];
+            jbq = src[8 * jn + 3];
+            jc = src[8 * jn + 4];
+          } else {
+            // padding nodes (only in the last tile, which never meets
+            // padding targets here): far below every node, no tensor
+            xj = xs[nn - 1];
+            yj = ys[nn - 1] - 1.0e3 * (double)(lane + 1);
+            ja = jbq = jc = 0.0;
+          }
+          double bx = 0.0, by = 0.0;
+          for (int k = 0; k < kTileLanes; ++k) {
+            sym_pairs<T>(xi, yi, qa, qb, qc, xj, yj, ja, jbq, jc, ax, ay, bx, by);
+            xj = ring_next(xj);
+            yj = ring_next(yj);
+            ja = ring_next(ja);
+            jbq = ring_next(jbq);
+            jc = ring_next(jc);
+            bx = ring_next(bx);
+            by = ring_next(by);
+          }
+          rev[tj][0][jl] -= bx;
+          rev[tj][1][jl] -= by;
+        }
+      }
+    }
+    // the row tile's sums: waves 1..3 through LDS to wave 0, in a fixed order
+    if (wv > 0) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        red[wv - 1][2 * t][lane] = ax[t];
+        red[wv - 1][2 * t + 1][lane] = ay[t];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int o = 0; o < kWaves - 1; ++o)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          ax[t] += red[o][2 * t][lane];
+          ay[t] += red[o][2 * t + 1][lane];
+        }
+      double *po = P + ((int64_t)Kr * (R + 1) + (Kcu - Kr)) * slot_doubles + (int64_t)ti * kSymTile;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        po[lane + t * kTileLanes] = ax[t];
+        po[kSymSBN + lane + t * kTileLanes] = ay[t];
+      }
+    }
+    __syncthreads();
+  }
+  // the column tiles' sums
+  double *pc = P + ((int64_t)Kcu * (R + 1) + (R - Kcu) + Kr) * slot_doubles;
+  for (int tj = 0; tj < kSymSB; ++tj) {
+    if (Kcu * kSymSB + tj >= ntiles) break;
+    for (int e = threadIdx.x; e < kSymTile; e += blockDim.x) {
+      pc[(int64_t)tj * kSymTile + e] = rev[tj][0][e];
+      pc[kSymSBN + (int64_t)tj * kSymTile + e] = rev[tj][1][e];
+    }
+  }
+}
+
+// part[i], part[nn + i] = the R + 1 slots of node i, added in slot order.
+__global__ void sym_reduce(const double *__restrict__ P, int64_t nn, int R, double *__restrict__ part) {
+  constexpr int sbn = kSymSBN;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int64_t K = i / sbn, il = i - K * sbn;
+  const double *p = P + K * (R + 1) * 2 * (int64_t)sbn + il;
+  double sx = 0.0, sy = 0.0;
+  for (int s = 0; s <= R; ++s) {
+    sx += p[(int64_t)s * 2 * sbn];
+    sy += p[(int64_t)s * 2 * sbn + sbn];
+  }
+  part[i] = sx;
+  part[nn + i] = sy;
+}
+
 // Stokeslet + rotlet columns: sum over pores of S(x_i - c_k) lambda_k
 // + r_k R(x_i - c_k) mu_k, without the 1/(4 pi) (applied in the epilogue).
 template <bool ACC>
@@ -560,10 +780,25 @@ int choose_chunks(int64_t nn, int64_t tiles, int tpt) {
   return (int)c;
 }
 
-MatvecWork plan_matvec(const sbie_geom *g) {
+MatvecWork plan_matvec(const sbie_geom *g, bool allow_sym) {
   MatvecWork w;
   w.tpt = g_tpt;
   const int64_t nn = g->n_nodes;
+  // symmetric evaluation: one superblock pair per workgroup needs enough
+  // pairs to fill the device (from about 16k nodes), and its partial sums
+  // grow as nn^2 / 1024 doubles (bounded here by 128 superblocks, 131,072
+  // nodes, 270 MB); the explicit chunk count of the launch-shape hook asks
+  // for the chunked kernel
+  const int64_t ntiles = (nn + kSymTile - 1) / kSymTile;
+  const int64_t R = (ntiles + kSymSB - 1) / kSymSB;
+  if (allow_sym && g_chunks == 0 && R <= 128 &&
+      (g_sym_mode == 2 || (g_sym_mode == 1 && nn >= 16384))) {
+    w.sym = 1;
+    w.sym_R = (int)R;
+    w.chunks = 1;
+    w.pchunks = g->n_pores > 0 ? (int)ceil_div(g->n_pores, kPoreChunk) : 0;
+    return w;
+  }
   const int64_t tiles = ceil_div(nn, (int64_t)kTileLanes * w.tpt);
   if (g_chunks > 0) {
     w.chunks = g_chunks;
@@ -578,7 +813,8 @@ MatvecWork plan_matvec(const sbie_geom *g) {
 size_t matvec_scratch_doubles(const MatvecWork &w, const sbie_geom *g) {
   const int64_t nn = g->n_nodes;
   return (size_t)8 * nn + (size_t)8 * (g->n_pores + 1) +
-         (size_t)(w.chunks + w.pchunks) * 4 * nn + 8;
+         (size_t)(w.chunks + w.pchunks) * 4 * nn + 8 +
+         (w.sym ? (size_t)w.sym_R * (w.sym_R + 1) * 2 * kSymSBN : 0);
 }
 
 void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
@@ -589,6 +825,7 @@ void bind_matvec_scratch(MatvecWork &w, const sbie_geom *g, double *base) {
   w.psrc = w.src + 8 * nn;
   w.scal = w.psrc + 8 * (g->n_pores + 1);
   w.part = w.scal + 8;
+  w.sym_buf = w.sym ? w.part + (size_t)(w.chunks + w.pchunks) * 4 * nn : nullptr;
 }
 
 void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
@@ -611,6 +848,8 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
   }
   const int64_t chunk = (nn + w.chunks - 1) / w.chunks;
   const int tiles = (int)ceil_div(nn, (int64_t)kTileLanes * w.tpt);
+  if (w.sym && acc)
+    fail(SBIE_INVALID_ARGUMENT, "the compensated product needs a chunked plan (plan_matvec with allow_sym off)");
   const int xcd = (w.chunks % 8 == 0) ? 1 : 0;
   const unsigned grid = (unsigned)((int64_t)tiles * w.chunks);
   const int tiles1 = (int)ceil_div(nn, kTileLanes);
@@ -626,6 +865,15 @@ void matvec_run(const sbie_geom *g, const double *x, double *y, int mode,
   }
   if (pairs) {
     pairs->run(w.src, w.part, s);
+  } else if (w.sym && !acc) {
+    const int ntiles = (int)ceil_div(nn, kSymTile);
+    const int R = w.sym_R;
+    if ((int64_t)R * kSymSB < ntiles || w.chunks != 1 || !w.sym_buf)
+      fail(SBIE_INVALID_ARGUMENT, "symmetric pair plan does not match the geometry");
+    dlp_pairs_sym<<<(unsigned)((int64_t)R * (R + 1) / 2), kBlock, 0, s>>>(w.src, g->x, g->y, nn, ntiles, R,
+                                                                          w.sym_buf);
+    SBIE_LAUNCH_CHECK();
+    sym_reduce<<<ceil_div(nn, 256), 256, 0, s>>>(w.sym_buf, nn, R, w.part);
   } else if (acc) {
     dlp_pairs<1, true><<<grid1, kBlock, 0, s>>>(w.src, g->x, g->y, nn, nn, chunk, w.part, tiles1, xcd);
   } else {
@@ -840,7 +1088,7 @@ BatchMatvec::BatchMatvec(const sbie_geom *const *g, int count) {
   std::vector<size_t> offs;
   for (int b = 0; b < count; ++b) {
     geoms.push_back(g[b]);
-    work.push_back(plan_matvec(g[b]));
+    work.push_back(plan_matvec(g[b], false));
     work.back().tpt = tpt;
     offs.push_back(total);
     total += (matvec_scratch_doubles(work.back(), g[b]) + 31) & ~size_t(31);
@@ -985,7 +1233,7 @@ extern "C" int stokes_dlp_matvec(const sbie_geom *g, const double *x, double *y,
     if (x < y + n && y < x + n)
       sbie::fail(SBIE_INVALID_ARGUMENT, "x and y overlap");
     hipStream_t s = (hipStream_t)stream;
-    sbie::MatvecWork w = sbie::plan_matvec(g);
+    sbie::MatvecWork w = sbie::plan_matvec(g, mode != SBIE_MV_FULL_ACCURATE);
     sbie::StreamBuf<double> scratch(sbie::matvec_scratch_doubles(w, g), s);
     sbie::bind_matvec_scratch(w, g, scratch.p);
     sbie::matvec_run(g, x, y, mode, w, s);
@@ -1034,7 +1282,7 @@ extern "C" int stokes_dlp_matvec_noalloc(const sbie_geom *g, const double *x, do
       sbie::fail(SBIE_INVALID_ARGUMENT, "unknown matvec mode %d", mode);
     const int64_t n = sbie::n_unknowns(g);
     if (x < y + n && y < x + n) sbie::fail(SBIE_INVALID_ARGUMENT, "x and y overlap");
-    sbie::MatvecWork w = sbie::plan_matvec(g);
+    sbie::MatvecWork w = sbie::plan_matvec(g, false);
     // fit the source chunks into the fixed array: records and scalars, then
     // one partial sum (2 or 4 doubles per node) per pair and pore chunk
     const int64_t nn = g->n_nodes;
@@ -1109,6 +1357,27 @@ extern "C" int stokes_dlp_matvec_set_shape(int targets_per_thread,
     if (source_chunks < 0) sbie::fail(SBIE_INVALID_ARGUMENT, "source_chunks < 0");
     sbie::g_tpt = targets_per_thread;
     sbie::g_chunks = source_chunks;
+    return SBIE_OK;
+  });
+}
+
+extern "C" int stokes_dlp_matvec_describe_plan(const sbie_geom *g, int mode, int32_t *symmetric, int32_t *chunks,
+                                              int32_t *targets_per_thread) {
+  return sbie::guarded([&]() {
+    sbie::validate_geom(g);
+    if (!symmetric || !chunks || !targets_per_thread) sbie::fail(SBIE_INVALID_ARGUMENT, "null pointer");
+    const sbie::MatvecWork w = sbie::plan_matvec(g, mode != SBIE_MV_FULL_ACCURATE);
+    *symmetric = w.sym;
+    *chunks = w.chunks;
+    *targets_per_thread = w.sym ? sbie::kSymT : (mode == SBIE_MV_FULL_ACCURATE ? 1 : w.tpt);
+    return SBIE_OK;
+  });
+}
+
+extern "C" int stokes_dlp_matvec_set_symmetric(int mode) {
+  return sbie::guarded([&]() {
+    if (mode < 0 || mode > 2) sbie::fail(SBIE_INVALID_ARGUMENT, "mode must be 0, 1 or 2");
+    sbie::g_sym_mode = mode;
     return SBIE_OK;
   });
 }
