@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
 template <class T>
 struct PanelDesc {
   T *A;          // n x n, ld n
-  T *work;       // (n - k0) x pb scratch
+  T *work;       // n x pb scratch
   int *ipiv;     // n entries (column chosen at step k; fallback kernel only)
   int *lab;      // n entries: original column now at each position
   int n, k0, pb;
@@ -1118,19 +1118,24 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const PanelDesc<T> *__
   }
 }
 
-// Same result for panels of at most kPanelRegRows columns, with two barriers
-// per step instead of a dozen: each of 256 threads keeps up to three
-// columns of the panel in registers (column j belongs to thread j % 256,
-// slot j / 256; a column's pb entries are contiguous in memory).  Below,
-// "row" names such a register vector: the elimination is the one of the
-// transposed panel.  A step takes a wave-shuffle argmax, one barrier to
-// combine the four waves, then the owner of the pivot vector posts it in LDS
-// and, after the second barrier, every thread updates its unused vectors.
-// Vectors never move between threads; the choice order alone defines the
-// interchanges.  LDS buffers alternate between steps, so the next step's
-// posts cannot overwrite what a slower wave still reads.  Finally the
+// The same elimination for panels of at most kPanelRegRows columns, one
+// workgroup barrier per step: each thread keeps one column of the panel in
+// registers (column j belongs to thread j; a column's pb entries are
+// contiguous in memory), in workgroups of 256, 512 or 768 threads by the
+// panel's height.  Below, "row"
+// names such a register vector: the elimination is the one of the
+// transposed panel.  The pivot is the largest |entry| (a non-finite one
+// counts as +inf and stops the panel), the lowest row among equal ones: a
+// maximum of doubles and then a minimum of row numbers over each wave, both
+// by DPP.  The owner of each wave's best candidate posts its row to LDS
+// before the barrier, so after it every thread knows the winner and its row
+// at once.  Vectors never move between
+// threads; the choice order alone defines the interchanges.  The steps run
+// in a loop of four expanded steps, after which the register columns shift
+// by four: the code stays small enough for the instruction cache (the fully
+// expanded 32 steps were bound by instruction fetch).  Finally the
 // interchanges are applied to A as one permutation of the touched columns,
-// staged through LDS in blocks of 64 rows.
+// in three passes separated by barriers (see the end of the kernel).
 template <int I, int N, class F>
 __device__ __forceinline__ void static_for(F &&f) {
   if constexpr (I < N) {
@@ -1139,12 +1144,10 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
-// Four waves with three vectors per lane (panels of up to 768 columns).  A
-// single wave with six vectors per lane (no workgroup barriers) measured
-// slower: the steps are bound by their own latency chain, not the barriers.
-constexpr int kPanelThreads = 256;
-constexpr int kPanelSlots = 3;
-constexpr int kPanelRegRows = kPanelThreads * kPanelSlots;
+// One vector per thread (panels of up to 768 columns).  Three vectors per
+// thread in a 256-thread workgroup spilled registers once the steps became
+// a loop; a single wave with six vectors per lane measured slower.
+constexpr int kPanelRegRows = 768;
 
 // workgroup barrier; for a single wave, LDS completion and a wave barrier
 template <int THREADS>
@@ -1157,17 +1160,54 @@ __device__ __forceinline__ void panel_sync() {
   }
 }
 
+// a double moved between lanes by the DPP control CTRL (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Maximum over the 64 lanes of a wave, returned in every lane (all lanes
+// active, no NaN inputs): lane pairs, quads, half rows and rows of 16 by
+// DPP, then the four row maxima read from lanes 0, 16, 32 and 48.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Minimum of an int over the 64 lanes of a wave, returned in every lane
+// (all lanes active), by the same exchanges.
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
 template <class T, int THREADS, int SLOTS>
 __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDesc<T> *__restrict__ descs) {
   constexpr int PB = 32;
+  constexpr int U = 4;   // expanded steps per loop iteration
   constexpr int NW = THREADS / 64;
+  static_assert(PB % U == 0, "the panel width is a multiple of the expanded steps");
   const PanelDesc<T> d = descs[blockIdx.x];
-  __shared__ double w_v[2][NW];
-  __shared__ int w_i[2][NW];
-  __shared__ T prow[2][PB];
+  __shared__ double w_val[2][NW];
+  __shared__ int w_idx[2][NW];
+  __shared__ T w_row[2][NW][PB];
   __shared__ int chosen[PB];
   __shared__ int u_pos[2 * PB], u_src[2 * PB];
-  __shared__ int s_nu;
+  __shared__ int s_nu, s_na;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int h = d.n - d.k0, pb = d.pb;
   T row[SLOTS][PB];
@@ -1178,71 +1218,79 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
     for (int c = 0; c < PB; ++c)
       row[q][c] = (r < h && c < pb) ? d.A[(d.k0 + c) + (size_t)(d.k0 + r) * d.n] : T(0);
   }
-  // one step per column, expanded at compile time (static_for) so that every
-  // column index is a constant and the rows stay in registers.  Rows never
-  // trade places during the elimination: a chosen row is marked as used
-  // (bit q of `used`) and posted to LDS, and only unused rows are updated.
   bool failed = false;
-  unsigned used = 0;
-  static_for<0, PB>([&](auto tc) {
-    constexpr int t = decltype(tc)::value;
-    if (failed || t >= pb) return;
-    const int par = t & 1;
-    // argmax of |row[t]| over the unused rows (lowest row on ties)
-    double v = -1.0;
-    int bi = 0x7fffffff;
+  unsigned used = 0;   // bit q: slot q's vector has been chosen
+  for (int t0 = 0; t0 < pb; t0 += U) {
+    static_for<0, U>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;   // register column of step t
+      const int t = t0 + j;
+      if (failed || t >= pb) return;
+      const int par = t & 1;
+      // this thread's best candidate (lowest row on ties)
+      double v = -1.0;
+      int bi = 0x7fffffff, qb = -1;
 #pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int r = tid + THREADS * q;
-      const double a = fabs((double)row[q][t]);
-      if (r < h && !((used >> q) & 1u) && a > v) { v = a; bi = r; }
-    }
-    // butterfly: every lane ends with the wave's argmax
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(v, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
-    }
-    double pv = v;
-    int p = bi;
-    if constexpr (NW > 1) {
-      if (lane == 0) { w_v[par][wv] = v; w_i[par][wv] = bi; }
+      for (int q = 0; q < SLOTS; ++q) {
+        const int r = tid + THREADS * q;
+        if (r < h && !((used >> q) & 1u)) {
+          double a = fabs((double)row[q][j]);
+          if (!isfinite(a)) a = HUGE_VAL;
+          if (a > v) { v = a; bi = r; qb = q; }
+        }
+      }
+      const double wmax = wave_max_f64(v);
+      const int wrow = wave_min_i32(v == wmax ? bi : 0x7fffffff);
+      // one owner per wave: the lowest row holding the wave's maximum
+      if (qb >= 0 && bi == wrow) {
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+          if (q == qb) {
+#pragma unroll
+            for (int c = 0; c < PB; ++c) w_row[par][wv][c] = row[q][c];
+          }
+      }
+      if (lane == 0) {
+        w_val[par][wv] = wmax;
+        w_idx[par][wv] = wrow;
+      }
       __syncthreads();
-      pv = w_v[par][0];
-      p = w_i[par][0];
+      double pv = w_val[par][0];
+      int p = w_idx[par][0], wb = 0;
 #pragma unroll
-      for (int w = 1; w < NW; ++w)
-        if (w_v[par][w] > pv || (w_v[par][w] == pv && w_i[par][w] < p)) { pv = w_v[par][w]; p = w_i[par][w]; }
-    }
-    if (!(pv > 0.0) || !isfinite(pv)) {
-      if (tid == 0) *d.info = d.k0 + t + 1;
-      failed = true;
-      return;
-    }
-    if (tid == 0) chosen[t] = p;
-    // the owner posts the pivot row
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      if (tid + THREADS * q == p) {
-#pragma unroll
-        for (int c = t; c < PB; ++c) prow[par][c] = row[q][c];
-        used |= 1u << q;
+      for (int w = 1; w < NW; ++w) {
+        const double ov = w_val[par][w];
+        const int oi = w_idx[par][w];
+        if (ov > pv || (ov == pv && oi < p)) { pv = ov; p = oi; wb = w; }
       }
-    }
-    panel_sync<THREADS>();
-    const T pinv = T(1) / prow[par][t];
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int r = tid + THREADS * q;
-      if (r < h && !((used >> q) & 1u)) {
-        const T l = row[q][t] * pinv;
-        row[q][t] = l;
-#pragma unroll
-        for (int c = t + 1; c < PB; ++c) row[q][c] = fma(-l, prow[par][c], row[q][c]);
+      if (!(pv > 0.0) || !isfinite(pv)) {
+        if (tid == 0) *d.info = d.k0 + t + 1;
+        failed = true;
+        return;
       }
-    }
-  });
-  if (failed) return;
+      if (tid == 0) chosen[t] = p;
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+        if (tid + THREADS * q == p) used |= 1u << q;
+      const T *prow = w_row[par][wb];
+      const T pinv = T(1) / prow[j];
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) {
+        const int r = tid + THREADS * q;
+        if (r < h && !((used >> q) & 1u)) {
+          const T l = row[q][j] * pinv;
+          row[q][j] = l;
+#pragma unroll
+          for (int c = j + 1; c < PB; ++c) row[q][c] = fma(-l, prow[c], row[q][c]);
+        }
+      }
+    });
+    if (failed) return;   // uniform: every thread read the same keys
+    // the next iteration's columns move to register columns 0..U-1
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+      for (int c = 0; c < PB; ++c) row[q][c] = c + U < PB ? row[q][c + U] : T(0);
+  }
   // the panel's permutation of columns: position k0 + t receives the t-th
   // chosen column; the columns of [k0, k0 + pb) that were not chosen move,
   // in increasing order, to the positions that chosen columns from beyond
@@ -1259,6 +1307,7 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
         u_src[nu] = d.k0 + chosen[t];
         ++nu;
       }
+    s_na = nu;
     int x = 0;
     for (int t = 0; t < pb; ++t)
       if (chosen[t] >= pb) {
@@ -1271,7 +1320,7 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
     s_nu = nu;
   }
   panel_sync<THREADS>();
-  const int nu = s_nu;
+  const int nu = s_nu, na = s_na;
   if (nu == 0) return;
   {
     // the column labels follow the same permutation (all reads before the
@@ -1280,22 +1329,20 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
     panel_sync<THREADS>();
     if (tid < nu) d.lab[u_pos[tid]] = v;
   }
-  // blocks of 64 rows staged through LDS: all touched values of the block
-  // are loaded before any is stored; each column segment is one coalesced
-  // 512-byte access
-  __shared__ T stage[2 * PB][64];
-  for (int r0 = 0; r0 < d.n; r0 += 64) {
-    for (int e = tid; e < nu * 64; e += THREADS) {
-      const int i = e >> 6, r = r0 + (e & 63);
-      if (r < d.n) stage[i][e & 63] = d.A[r + (size_t)u_src[i] * d.n];
-    }
-    panel_sync<THREADS>();
-    for (int e = tid; e < nu * 64; e += THREADS) {
-      const int i = e >> 6, r = r0 + (e & 63);
-      if (r < d.n) d.A[r + (size_t)u_pos[i] * d.n] = stage[i][e & 63];
-    }
-    panel_sync<THREADS>();
-  }
+  // Entries [0, na) move chosen columns into the panel, entries [na, nu)
+  // move the panel's unchosen columns to the places the chosen ones left
+  // beyond the panel.  The sources of the first group are saved to the
+  // scratch columns, the second group is copied (its sources lie in the
+  // panel, its destinations beyond it), then the first group is written
+  // from the scratch copy.  Accesses are whole columns, coalesced.
+  for (int i = 0; i < na; ++i)
+    for (int r = tid; r < d.n; r += THREADS) d.work[r + (size_t)i * d.n] = d.A[r + (size_t)u_src[i] * d.n];
+  __syncthreads();
+  for (int i = na; i < nu; ++i)
+    for (int r = tid; r < d.n; r += THREADS) d.A[r + (size_t)u_pos[i] * d.n] = d.A[r + (size_t)u_src[i] * d.n];
+  __syncthreads();
+  for (int i = 0; i < na; ++i)
+    for (int r = tid; r < d.n; r += THREADS) d.A[r + (size_t)u_pos[i] * d.n] = d.work[r + (size_t)i * d.n];
 }
 
 template <class T>
@@ -1653,14 +1700,19 @@ __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs
 // panel, so the diagonal already holds the pivots an interchanging
 // elimination of the transposed block would take (the pivots of an
 // elimination without interchanges are ratios of leading principal minors,
-// the same for a matrix and its transpose).  Lane i keeps row i in
-// registers; the scaled pivot row is broadcast through LDS.
+// the same for a matrix and its transpose).  Lane i keeps row i of
+// diag(M, I) (order NMAX) in registers; the scaled pivot row is broadcast
+// through LDS.  The steps run in a loop of U expanded steps, after which the
+// register columns rotate by U (NMAX steps rotate them back into place): the
+// code stays small enough for the instruction cache.
 template <class T, int NMAX>
 __global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict__ ptrs,
                                                            const int *__restrict__ ns,
                                                            int32_t *__restrict__ info,
                                                            const T *const *__restrict__ srcs,
                                                            const int *__restrict__ lds) {
+  constexpr int U = 8;
+  static_assert(NMAX % U == 0 && NMAX <= 64, "the order is a multiple of the expanded steps");
   __shared__ T prow[2][NMAX];
   const int b = blockIdx.x;
   const int n = ns[b];
@@ -1670,39 +1722,47 @@ __global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict_
   const int i = threadIdx.x;
   T r[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : T(0);
-  bool failed = false;
-  static_for<0, NMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (failed || k >= n) return;
-    constexpr int par = k & 1;
-    if (i == k) {
-      const T inv = T(1) / r[k];
-      r[k] = T(1);
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : (i == c ? T(1) : T(0));
+  int fail_at = 0;   // 1 + the first step with a zero or non-finite pivot
+  for (int k0 = 0; k0 < NMAX; k0 += U) {
+    static_for<0, U>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;   // register column of step k
+      constexpr int par = j & 1;
+      const int k = k0 + j;
+      if (i == k) {
+        const T inv = T(1) / r[j];
+        r[j] = T(1);
 #pragma unroll
-      for (int c = 0; c < NMAX; ++c) {
-        r[c] *= inv;
-        prow[par][c] = r[c];
+        for (int c = 0; c < NMAX; ++c) {
+          r[c] *= inv;
+          prow[par][c] = r[c];
+        }
       }
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the row is in LDS
-    __builtin_amdgcn_wave_barrier();
-    // prow[k] holds 1 / pivot: a zero pivot fails here.  (No early return
-    // inside the expanded loop: with one, the compiler keeps every step's
-    // values live and spills them; the next step's test skips the rest.)
-    if (!isfinite((double)prow[par][k])) {
-      if (i == 0) info[b] = k + 1;
-      failed = true;
-    }
-    if (i != k && i < n) {
-      const T f = r[k];
-      r[k] = T(0);
+      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the row is in LDS
+      __builtin_amdgcn_wave_barrier();
+      // prow[j] holds 1 / pivot; the elimination runs on (its values are
+      // discarded after a failure)
+      if (fail_at == 0 && !isfinite((double)prow[par][j])) fail_at = k + 1;
+      if (i != k) {
+        const T f = r[j];
+        r[j] = T(0);
 #pragma unroll
-      for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[par][c], r[c]);
-    }
-    __builtin_amdgcn_wave_barrier();
-  });
-  if (failed) return;
+        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[par][c], r[c]);
+      }
+      __builtin_amdgcn_wave_barrier();
+    });
+    T head[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) head[c] = r[c];
+#pragma unroll
+    for (int c = 0; c + U < NMAX; ++c) r[c] = r[c + U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) r[NMAX - U + c] = head[c];
+  }
+  if (fail_at) {
+    if (i == 0) info[b] = fail_at;
+    return;
+  }
   if (i < n) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
@@ -1906,8 +1966,12 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       const Step &q = steps[it];
       const auto *dd = (const PanelDesc<T> *)(db + q.pd);
       static_assert(kPanel <= 32, "the register panels hold 32 entries per vector");
-      if (q.hmax <= kPanelRegRows)                                      // choose columns, swap
-        panel_pivot_reg_kernel<T, kPanelThreads, kPanelSlots><<<(unsigned)q.npd, kPanelThreads, 0, s>>>(dd);
+      if (q.hmax <= 256)                                                // choose columns, swap
+        panel_pivot_reg_kernel<T, 256, 1><<<(unsigned)q.npd, 256, 0, s>>>(dd);
+      else if (q.hmax <= 512)
+        panel_pivot_reg_kernel<T, 512, 1><<<(unsigned)q.npd, 512, 0, s>>>(dd);
+      else if (q.hmax <= kPanelRegRows)
+        panel_pivot_reg_kernel<T, 768, 1><<<(unsigned)q.npd, 768, 0, s>>>(dd);
       else
         panel_pivot_kernel<T><<<(unsigned)q.npd, 256, 0, s>>>(dd);
       SBIE_LAUNCH_CHECK();
