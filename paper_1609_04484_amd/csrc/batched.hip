@@ -497,16 +497,51 @@ __global__ __launch_bounds__(256) void copy_desc(const CopyDesc<T> *__restrict__
   }
 }
 
+// Sum of squares of NR entries per column (rows 0, 256, ..., 256 (NR - 1)
+// of A) over `cols` columns, accumulated in column order and, within a
+// column, in row order; the loads of several columns are issued before
+// their products are added, so they are in flight together.
+template <class T, int NR>
+__device__ __forceinline__ double sumsq_cols(const T *A, int lda, int cols) {
+  constexpr int UC = NR == 1 ? 8 : (NR == 2 ? 4 : 3);
+  double s = 0.0;
+  int c = 0;
+  for (; c + UC <= cols; c += UC) {
+    double v[UC][NR];
+#pragma unroll
+    for (int u = 0; u < UC; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[u][k] = (double)A[256 * k + (size_t)(c + u) * lda];
+#pragma unroll
+    for (int u = 0; u < UC; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) s = fma(v[u][k], v[u][k], s);
+  }
+  for (; c < cols; ++c)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double v = (double)A[256 * k + (size_t)c * lda];
+      s = fma(v, v, s);
+    }
+  return s;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void norm_desc(const NormDesc<T> *__restrict__ descs,
                                                  double *__restrict__ out) {
   const NormDesc<T> d = descs[blockIdx.x];
+  const int t = threadIdx.x;
+  const int nr = t < d.rows ? (d.rows - 1 - t) / 256 + 1 : 0;   // rows of this thread per column
   double s = 0.0;
-  for (int c = 0; c < d.cols; ++c)
-    for (int r = threadIdx.x; r < d.rows; r += 256) {
-      const double v = (double)d.A[r + (size_t)c * d.lda];
-      s = fma(v, v, s);
-    }
+  if (nr == 1) s = sumsq_cols<T, 1>(d.A + t, d.lda, d.cols);
+  else if (nr == 2) s = sumsq_cols<T, 2>(d.A + t, d.lda, d.cols);
+  else if (nr == 3) s = sumsq_cols<T, 3>(d.A + t, d.lda, d.cols);
+  else if (nr > 3)
+    for (int c = 0; c < d.cols; ++c)
+      for (int r = t; r < d.rows; r += 256) {
+        const double v = (double)d.A[r + (size_t)c * d.lda];
+        s = fma(v, v, s);
+      }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -706,6 +741,44 @@ __global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ pt
 // In FP32 every accepted column is projected out of the candidates in place
 // (see pgs_kernel).  Reductions go through wave shuffles, then across the 16
 // waves in LDS.
+// a double moved between lanes by the DPP control CTRL (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Maximum over the 64 lanes of a wave, returned in every lane (all lanes
+// active, no NaN inputs): lane pairs, quads, half rows and rows of 16 by
+// DPP, then the four row maxima read from lanes 0, 16, 32 and 48.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Minimum of an int over the 64 lanes of a wave, returned in every lane
+// (all lanes active), by the same exchanges.
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// An empty instruction that takes the 32 values as operands: every value
+// must be in a register at this point, so their loads are issued together
+// instead of one or two at a time between the arithmetic that uses them.
 constexpr int kPgsThreads = 1024;
 constexpr int kPgsWaves = kPgsThreads / 64;
 
@@ -858,6 +931,8 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
   __shared__ double dots[kPgsChunk][B];
   __shared__ double vsel[B], nsq[B];
   __shared__ int psel[B];
+  __shared__ double cand_v[kPgsWaves][B];
+  __shared__ int cand_i[kPgsWaves][B];
   __shared__ int nsel, nacc;
   __shared__ double red_v[kPgsWaves];
   __shared__ int red_i[kPgsWaves];
@@ -874,34 +949,46 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
   const int c0 = min(d.orth_from, d.r0);
   int k = 0;
   for (int guard = 0; guard < d.c + d.rmax && d.r0 + k < d.rmax; ++guard) {
-    // 1. up to B pivots, largest residual norm first (lowest index on ties)
+    // 1. up to B pivots, largest residual norm first (lowest index on ties):
+    // each wave lists its own best `room` candidates in that order (DPP
+    // maximum of the norms, then minimum of the indices holding it), then
+    // wave 0 merges the sorted lists by their heads; a candidate must
+    // exceed -1 (taken) and be a number, and the picks stop at the first
+    // one not above the tolerance.
     const int room = min(B, d.rmax - d.r0 - k);
-    int ns = 0;
-    for (; ns < room; ++ns) {
-      double best = -1.0;
-      int bi = 0;
-      for (int j = tid; j < d.c; j += kPgsThreads)
-        if (norms[j] > best) { best = norms[j]; bi = j; }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_down(best, o, 64);
-        const int oi = __shfl_down(bi, o, 64);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    {
+      unsigned long long removed = 0;   // bit q: entry tid + q kPgsThreads listed
+      for (int i = 0; i < room; ++i) {
+        double v = -1.0;
+        int bi = 0x7fffffff, bq = -1;
+        for (int q = 0, j = tid; j < d.c; j += kPgsThreads, ++q)
+          if (!((removed >> q) & 1ull) && norms[j] > v) { v = norms[j]; bi = j; bq = q; }
+        const double wmax = wave_max_f64(v);
+        const int wi = wave_min_i32(v == wmax ? bi : 0x7fffffff);
+        if (lane == 0) { cand_v[wv][i] = wmax; cand_i[wv][i] = wi; }
+        if (bq >= 0 && bi == wi) removed |= 1ull << bq;
       }
-      if (lane == 0) { red_v[wv] = best; red_i[wv] = bi; }
-      __syncthreads();
-      double vmax = red_v[0];
-      int p = red_i[0];
-      for (int w = 1; w < kPgsWaves; ++w)
-        if (red_v[w] > vmax || (red_v[w] == vmax && red_i[w] < p)) { vmax = red_v[w]; p = red_i[w]; }
-      __syncthreads();            // everyone has read red_v / red_i
-      if (!(vmax > tol2)) break;  // uniform
-      if (tid == 0) {
-        vsel[ns] = vmax;
-        psel[ns] = p;
-        norms[p] = -1.0;          // taken (restored below if not accepted)
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    if (wv == 0) {
+      int head = 0, cnt = 0;            // lane w < kPgsWaves walks wave w's list
+      for (; cnt < room; ++cnt) {
+        const double hv = (lane < kPgsWaves && head < room) ? cand_v[lane][head] : -1.0;
+        const int hi = (lane < kPgsWaves && head < room) ? cand_i[lane][head] : 0x7fffffff;
+        const double vmax = wave_max_f64(hv);
+        const int p = wave_min_i32(hv == vmax ? hi : 0x7fffffff);
+        if (!(vmax > tol2)) break;      // uniform
+        if (lane < kPgsWaves && head < room && hi == p) ++head;
+        if (lane == 0) {
+          vsel[cnt] = vmax;
+          psel[cnt] = p;
+          norms[p] = -1.0;              // taken (retired below)
+        }
+      }
+      if (lane == 0) nsel = cnt;
+    }
+    __syncthreads();
+    const int ns = nsel;
     if (ns == 0) break;
     // 2. the block's columns into LDS
     for (int e = tid; e < ns * d.m; e += kPgsThreads) {
@@ -1160,39 +1247,14 @@ __device__ __forceinline__ void panel_sync() {
   }
 }
 
-// a double moved between lanes by the DPP control CTRL (both halves)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
-                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-// Maximum over the 64 lanes of a wave, returned in every lane (all lanes
-// active, no NaN inputs): lane pairs, quads, half rows and rows of 16 by
-// DPP, then the four row maxima read from lanes 0, 16, 32 and 48.
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
-  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
-  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
-  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
-  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
-}
-
-// Minimum of an int over the 64 lanes of a wave, returned in every lane
-// (all lanes active), by the same exchanges.
-__device__ __forceinline__ int wave_min_i32(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+template <class T>
+__device__ __forceinline__ void pin_registers(T (&v)[32]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+               "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+               "+v"(v[14]), "+v"(v[15]));
+  asm volatile("" : "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]), "+v"(v[20]), "+v"(v[21]),
+               "+v"(v[22]), "+v"(v[23]), "+v"(v[24]), "+v"(v[25]), "+v"(v[26]), "+v"(v[27]), "+v"(v[28]),
+               "+v"(v[29]), "+v"(v[30]), "+v"(v[31]));
 }
 
 template <class T, int THREADS, int SLOTS>
@@ -1254,13 +1316,21 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
         w_idx[par][wv] = wrow;
       }
       __syncthreads();
-      double pv = w_val[par][0];
-      int p = w_idx[par][0], wb = 0;
+      double wvals[NW];
+      int widx[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        wvals[w] = w_val[par][w];
+        widx[w] = w_idx[par][w];
+      }
+      double pv = wvals[0];
+      int p = widx[0], wb = 0;
 #pragma unroll
       for (int w = 1; w < NW; ++w) {
-        const double ov = w_val[par][w];
-        const int oi = w_idx[par][w];
-        if (ov > pv || (ov == pv && oi < p)) { pv = ov; p = oi; wb = w; }
+        const bool better = wvals[w] > pv || (wvals[w] == pv && widx[w] < p);
+        pv = better ? wvals[w] : pv;
+        p = better ? widx[w] : p;
+        wb = better ? w : wb;
       }
       if (!(pv > 0.0) || !isfinite(pv)) {
         if (tid == 0) *d.info = d.k0 + t + 1;
@@ -1271,7 +1341,11 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
 #pragma unroll
       for (int q = 0; q < SLOTS; ++q)
         if (tid + THREADS * q == p) used |= 1u << q;
-      const T *prow = w_row[par][wb];
+      // the whole pivot row is read at once (all loads in flight together)
+      T prow[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) prow[c] = c < j ? T(0) : w_row[par][wb][c];
+      pin_registers(prow);
       const T pinv = T(1) / prow[j];
 #pragma unroll
       for (int q = 0; q < SLOTS; ++q) {
@@ -1701,10 +1775,23 @@ __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs
 // elimination of the transposed block would take (the pivots of an
 // elimination without interchanges are ratios of leading principal minors,
 // the same for a matrix and its transpose).  Lane i keeps row i of
-// diag(M, I) (order NMAX) in registers; the scaled pivot row is broadcast
-// through LDS.  The steps run in a loop of U expanded steps, after which the
-// register columns rotate by U (NMAX steps rotate them back into place): the
-// code stays small enough for the instruction cache.
+// diag(M, I) (order NMAX) in registers; every lane reads the pivot row from
+// the pivot lane (readlane into scalar registers, no LDS round trip) and
+// scales it itself.  The steps run in a loop of U expanded steps, after
+// which the register columns rotate by U (NMAX steps rotate them back into
+// place): the code stays small enough for the instruction cache.
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int l);
+template <>
+__device__ __forceinline__ double lane_value<double>(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <>
+__device__ __forceinline__ float lane_value<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <class T, int NMAX>
 __global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict__ ptrs,
                                                            const int *__restrict__ ns,
@@ -1713,7 +1800,6 @@ __global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict_
                                                            const int *__restrict__ lds) {
   constexpr int U = 8;
   static_assert(NMAX % U == 0 && NMAX <= 64, "the order is a multiple of the expanded steps");
-  __shared__ T prow[2][NMAX];
   const int b = blockIdx.x;
   const int n = ns[b];
   T *A = ptrs[b];
@@ -1727,29 +1813,23 @@ __global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict_
   for (int k0 = 0; k0 < NMAX; k0 += U) {
     static_for<0, U>([&](auto jc) {
       constexpr int j = decltype(jc)::value;   // register column of step k
-      constexpr int par = j & 1;
       const int k = k0 + j;
-      if (i == k) {
-        const T inv = T(1) / r[j];
-        r[j] = T(1);
+      // pivot row k scaled by 1 / pivot, with 1 / pivot in column j
+      const T inv = T(1) / lane_value(r[j], k);
+      T pr[NMAX];
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) {
-          r[c] *= inv;
-          prow[par][c] = r[c];
-        }
-      }
-      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the row is in LDS
-      __builtin_amdgcn_wave_barrier();
-      // prow[j] holds 1 / pivot; the elimination runs on (its values are
-      // discarded after a failure)
-      if (fail_at == 0 && !isfinite((double)prow[par][j])) fail_at = k + 1;
-      if (i != k) {
+      for (int c = 0; c < NMAX; ++c) pr[c] = c == j ? inv : lane_value(r[c], k) * inv;
+      // the elimination runs on after a failure; its values are discarded
+      if (fail_at == 0 && !isfinite((double)inv)) fail_at = k + 1;
+      if (i == k) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) r[c] = pr[c];
+      } else {
         const T f = r[j];
         r[j] = T(0);
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[par][c], r[c]);
+        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, pr[c], r[c]);
       }
-      __builtin_amdgcn_wave_barrier();
     });
     T head[U];
 #pragma unroll
