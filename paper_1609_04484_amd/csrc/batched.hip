@@ -779,6 +779,20 @@ __device__ __forceinline__ int wave_min_i32(int v) {
 // An empty instruction that takes the 32 values as operands: every value
 // must be in a register at this point, so their loads are issued together
 // instead of one or two at a time between the arithmetic that uses them.
+// Sum over the wave as the shfl_down tree forms it (halving distances 32,
+// 16, ..., 1), exact in lane 0 only: the two long distances by permute, the
+// four within a row of 16 lanes by DPP row shifts (lane i receives lane
+// i + d), with the same additions in the same order.
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+  v += __shfl_down(v, 32, 64);
+  v += __shfl_down(v, 16, 64);
+  v += dpp_f64<0x108>(v);   // row_shl:8
+  v += dpp_f64<0x104>(v);   // row_shl:4
+  v += dpp_f64<0x102>(v);   // row_shl:2
+  v += dpp_f64<0x101>(v);   // row_shl:1
+  return v;
+}
+
 constexpr int kPgsThreads = 1024;
 constexpr int kPgsWaves = kPgsThreads / 64;
 
@@ -941,7 +955,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
     const double *col = d.R + (size_t)j * d.ldr;
     double s = 0.0;
     for (int i = lane; i < d.m; i += 64) s = fma(col[i], col[i], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    s = wave_sum_lane0(s);
     if (lane == 0) norms[j] = s;
   }
   __syncthreads();
@@ -1015,7 +1029,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
 #pragma unroll
           for (int s = 0; s < B; ++s) {
             double v = acc[s];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            v = wave_sum_lane0(v);
             if (lane == 0) dots[col - cb][s] = v;
           }
         }
@@ -1041,7 +1055,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
           const double *qt = Q + (size_t)t * d.m;
           double v = 0.0;
           for (int i = lane; i < d.m; i += 64) v = fma(qt[i], qs[i], v);
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+          v = wave_sum_lane0(v);
           if (lane == 0) dots[t][0] = v;
         }
         __syncthreads();
@@ -1054,7 +1068,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
       }
       double sq = 0.0;
       for (int i = tid; i < d.m; i += kPgsThreads) sq = fma(qs[i], qs[i], sq);
-      for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
+      sq = wave_sum_lane0(sq);
       if (lane == 0) red_v[wv] = sq;
       __syncthreads();
       double nq = 0.0;                       // same values, same order: uniform
@@ -1096,7 +1110,7 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
 #pragma unroll
       for (int s = 0; s < B; ++s) {
         double v = acc[s];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        v = wave_sum_lane0(v);
         dn = fma(v, v, dn);
       }
       if (lane == 0) norms[j] -= dn;
