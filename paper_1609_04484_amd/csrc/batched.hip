@@ -409,6 +409,84 @@ void launch_gemm_tiles(unsigned nt, const GemmDesc<T> *dd, const int2 *td, hipSt
 constexpr int kGemvThreads = 1024;
 constexpr int kGemvWaves = kGemvThreads / 64;
 
+// a double moved between lanes by the DPP control CTRL (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Maximum over the 64 lanes of a wave, returned in every lane (all lanes
+// active, no NaN inputs): lane pairs, quads, half rows and rows of 16 by
+// DPP, then the four row maxima read from lanes 0, 16, 32 and 48.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Minimum of an int over the 64 lanes of a wave, returned in every lane
+// (all lanes active), by the same exchanges.
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// An empty instruction that takes the 32 values as operands: every value
+// must be in a register at this point, so their loads are issued together
+// instead of one or two at a time between the arithmetic that uses them.
+// Lane i < 32 receives lane i + 32 (v_permlane32_swap of v with itself), and
+// lane i < 16 receives lane i + 16 (v_permlane16_swap); lane layouts checked
+// on the device.
+__device__ __forceinline__ double lane_plus32(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_permlane32_swap(hi, hi, false, false)[1],
+                          __builtin_amdgcn_permlane32_swap(lo, lo, false, false)[1]);
+}
+__device__ __forceinline__ double lane_plus16(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_permlane16_swap(hi, hi, false, false)[1],
+                          __builtin_amdgcn_permlane16_swap(lo, lo, false, false)[1]);
+}
+
+// Sum over the wave as the shfl_down tree forms it (halving distances 32,
+// 16, ..., 1), exact in lane 0 only: the two long distances by lane swaps,
+// the four within a row of 16 lanes by DPP row shifts (lane i receives lane
+// i + d), with the same additions in the same order.
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+  v += lane_plus32(v);
+  v += lane_plus16(v);
+  v += dpp_f64<0x108>(v);   // row_shl:8
+  v += dpp_f64<0x104>(v);   // row_shl:4
+  v += dpp_f64<0x102>(v);   // row_shl:2
+  v += dpp_f64<0x101>(v);   // row_shl:1
+  return v;
+}
+__device__ __forceinline__ float wave_sum_lane0(float v) {
+  auto mv = [](float x, auto ctrl) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), decltype(ctrl)::value, 0xF, 0xF, false));
+  };
+  v += __int_as_float(__builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false)[1]);
+  v += __int_as_float(__builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false)[1]);
+  v += mv(v, std::integral_constant<int, 0x108>{});
+  v += mv(v, std::integral_constant<int, 0x104>{});
+  v += mv(v, std::integral_constant<int, 0x102>{});
+  v += mv(v, std::integral_constant<int, 0x101>{});
+  return v;
+}
+
 template <class T, class TA>
 __global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__restrict__ descs,
                                                           const GemvTerm<T, TA> *__restrict__ terms) {
@@ -443,7 +521,7 @@ __global__ __launch_bounds__(kGemvThreads) void gemv_desc(const GemvDesc<T> *__r
         const TA *col = tm.A + (size_t)r * tm.lda;
         T s = T(0);
         for (int c = lane; c < tm.cols; c += 64) s = fma((T)col[c], tm.x[c], s);
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        s = wave_sum_lane0(s);
         if (lane == 0) accw[q] = fma(tm.alpha, s, accw[q]);
       }
     }
@@ -741,58 +819,6 @@ __global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ pt
 // In FP32 every accepted column is projected out of the candidates in place
 // (see pgs_kernel).  Reductions go through wave shuffles, then across the 16
 // waves in LDS.
-// a double moved between lanes by the DPP control CTRL (both halves)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
-                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-// Maximum over the 64 lanes of a wave, returned in every lane (all lanes
-// active, no NaN inputs): lane pairs, quads, half rows and rows of 16 by
-// DPP, then the four row maxima read from lanes 0, 16, 32 and 48.
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
-  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
-  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
-  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
-  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
-}
-
-// Minimum of an int over the 64 lanes of a wave, returned in every lane
-// (all lanes active), by the same exchanges.
-__device__ __forceinline__ int wave_min_i32(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
-// An empty instruction that takes the 32 values as operands: every value
-// must be in a register at this point, so their loads are issued together
-// instead of one or two at a time between the arithmetic that uses them.
-// Sum over the wave as the shfl_down tree forms it (halving distances 32,
-// 16, ..., 1), exact in lane 0 only: the two long distances by permute, the
-// four within a row of 16 lanes by DPP row shifts (lane i receives lane
-// i + d), with the same additions in the same order.
-__device__ __forceinline__ double wave_sum_lane0(double v) {
-  v += __shfl_down(v, 32, 64);
-  v += __shfl_down(v, 16, 64);
-  v += dpp_f64<0x108>(v);   // row_shl:8
-  v += dpp_f64<0x104>(v);   // row_shl:4
-  v += dpp_f64<0x102>(v);   // row_shl:2
-  v += dpp_f64<0x101>(v);   // row_shl:1
-  return v;
-}
-
 constexpr int kPgsThreads = 1024;
 constexpr int kPgsWaves = kPgsThreads / 64;
 
