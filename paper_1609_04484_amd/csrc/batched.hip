@@ -99,8 +99,8 @@ constexpr int kPanel = 32;
 // GEMM: one 64 x 64 output tile per workgroup, 256 threads (four waves, each a
 // 32 x 32 quarter), on the matrix cores
 // ----------------------------------------------------------------------------
-// FP64 GEMM tile: the output tile is staged through LDS in k-slabs of 16,
-// with each of the four waves computing a 32 x 32 quarter as
+// FP64 GEMM tile: the output tile is staged through LDS in k-slabs of 16
+// (double-buffered), with each of the four waves computing a 32 x 32 quarter as
 // 2 x 2 blocks of v_mfma_f64_16x16x4.  Operand layout of that instruction
 // (checked on the device): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16], and register v of lane l receives D[l / 16 + 4 v][l % 16].
@@ -113,8 +113,11 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *_
   const int tiles_m = (d.m + 63) >> 6;
   const int row0 = (tl.y % tiles_m) * 64;
   const int col0 = (tl.y / tiles_m) * 64;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  // two LDS stages: while one is multiplied out, the next k-slab's global
+  // values are loaded into registers and then stored into the other stage,
+  // so each slab takes one barrier
+  __shared__ double As[2][16][65];
+  __shared__ double Bs[2][16][65];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
@@ -123,8 +126,6 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *_
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-  // the next stage's global values are loaded into registers while the
-  // current stage is multiplied out of LDS
   double ra[4], rb[4];
   auto load_stage = [&](int k0) {
 #pragma unroll
@@ -140,33 +141,40 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *_
       rb[q] = (gj < d.n && gk2 < d.k) ? (d.tb ? d.B[gj + (size_t)gk2 * d.ldb] : d.B[gk2 + (size_t)gj * d.ldb]) : 0.0;
     }
   };
-  auto store_stage = [&]() {
+  auto store_stage = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
-      if (!d.ta) As[e >> 6][e & 63] = ra[q]; else As[e & 15][e >> 4] = ra[q];
-      if (!d.tb) Bs[e & 15][e >> 4] = rb[q]; else Bs[e >> 6][e & 63] = rb[q];
+      if (!d.ta) As[buf][e >> 6][e & 63] = ra[q]; else As[buf][e & 15][e >> 4] = ra[q];
+      if (!d.tb) Bs[buf][e & 15][e >> 4] = rb[q]; else Bs[buf][e >> 6][e & 63] = rb[q];
     }
   };
-  if (d.k > 0) load_stage(0);
-  for (int k0 = 0; k0 < d.k; k0 += 16) {
-    store_stage();
+  if (d.k > 0) {
+    load_stage(0);
+    store_stage(0);
     __syncthreads();
-    if (k0 + 16 < d.k) load_stage(k0 + 16);
+    int cur = 0;
+    for (int k0 = 0; k0 < d.k; k0 += 16) {
+      const bool more = k0 + 16 < d.k;
+      if (more) load_stage(k0 + 16);
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
-      double a[2], b[2];
+      for (int ks = 0; ks < 16; ks += 4) {
+        double a[2], b[2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        a[q] = As[ks + lk][wr + 16 * q + li];
-        b[q] = Bs[ks + lk][wc + 16 * q + li];
+        for (int q = 0; q < 2; ++q) {
+          a[q] = As[cur][ks + lk][wr + 16 * q + li];
+          b[q] = Bs[cur][ks + lk][wc + 16 * q + li];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
       }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+      // the other stage was last read before the previous barrier
+      if (more) store_stage(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
