@@ -106,8 +106,19 @@ constexpr int kPanel = 32;
 // B[l / 16][l % 16], and register v of lane l receives D[l / 16 + 4 v][l % 16].
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *__restrict__ descs,
-                                                       const int2 *__restrict__ tiles) {
+// Panel step of the blocked Gauss-Jordan (FP64): rows [k0, k0 + pb) of the
+// output take CP (pb x n, leading dimension pb), the other rows of columns
+// [k0, k0 + pb) take R (m x pb, leading dimension m), every other entry the
+// GEMM update; the values two copies and a product used to write over the
+// update afterwards.
+struct GjFix {
+  const double *R, *CP;
+  int k0, pb;
+};
+
+template <bool GJ>
+__device__ __forceinline__ void gemm_tile_f64(const GemmDesc<double> *__restrict__ descs,
+                                              const int2 *__restrict__ tiles, const GjFix *__restrict__ fixes) {
   const int2 tl = tiles[blockIdx.x];
   const GemmDesc<double> d = descs[tl.x];
   const int tiles_m = (d.m + 63) >> 6;
@@ -186,10 +197,32 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *_
         const int c = col0 + wc + 16 * y + li;
         if (r >= d.m || c >= d.n) continue;
         double *p = d.C + r + (size_t)c * d.ldc;
+        if constexpr (GJ) {
+          const GjFix &f = fixes[tl.x];
+          if (r >= f.k0 && r < f.k0 + f.pb) {
+            *p = f.CP[(r - f.k0) + (size_t)c * f.pb];
+            continue;
+          }
+          if (c >= f.k0 && c < f.k0 + f.pb) {
+            *p = f.R[r + (size_t)(c - f.k0) * d.m];
+            continue;
+          }
+        }
         double val = d.alpha * acc[x][y][v];
         if (d.beta != 0.0) val = fma(d.beta, *p, val);
         *p = val;
       }
+}
+
+__global__ __launch_bounds__(256) void gemm_tiles_mfma(const GemmDesc<double> *__restrict__ descs,
+                                                       const int2 *__restrict__ tiles) {
+  gemm_tile_f64<false>(descs, tiles, nullptr);
+}
+
+__global__ __launch_bounds__(256) void gemm_tiles_mfma_gj(const GemmDesc<double> *__restrict__ descs,
+                                                          const int2 *__restrict__ tiles,
+                                                          const GjFix *__restrict__ fixes) {
+  gemm_tile_f64<true>(descs, tiles, fixes);
 }
 
 // FP32 GEMM tile on the matrix cores: the same 64 x 64 tiles, LDS staging
@@ -1956,21 +1989,25 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
   std::vector<std::vector<int>> active(npan);
   size_t ws = 0;
   for (int n : bn) ws += (size_t)n * nb;
+  // FP64 panel steps take the fused update (R, -P C and the GEMM update in
+  // one launch; see gemm_tiles_mfma_gj), which needs -P C in its own buffer
+  constexpr bool fused = std::is_same<T, double>::value;
   StreamBuf<T> work(nbm ? ws : 0, s), C(nbm ? ws : 0, s), R(nbm ? ws : 0, s),
-      P(nbm ? (size_t)nbm * nb * nb : 0, s);
+      P(nbm ? (size_t)nbm * nb * nb : 0, s), CPb(nbm && fused ? ws : 0, s);
   StreamBuf<int> piv(nbm ? (size_t)nbm * maxn : 0, s), labb(nbm ? (size_t)nbm * maxn : 0, s);
   StreamBuf<T> negid(nbm ? (size_t)nb * nb : 0, s);   // -I of order nb
   if (nbm) {
     fill_value<T>(negid.p, (size_t)nb * nb, T(0), s);
     set_diagonal<T><<<1, 64, 0, s>>>(negid.p, nb, T(-1));
     SBIE_LAUNCH_CHECK();
-    std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm);
+    std::vector<T *> woff(nbm), coff(nbm), roff(nbm), poff(nbm), cpoff(nbm, nullptr);
     std::vector<int *> ipv(nbm), lbv(nbm);
     size_t o = 0;
     for (int b = 0; b < nbm; ++b) {
       woff[b] = work.p + o;
       coff[b] = C.p + o;
       roff[b] = R.p + o;
+      if (fused) cpoff[b] = CPb.p + o;
       o += (size_t)bn[b] * nb;
       poff[b] = P.p + (size_t)b * nb * nb;
       ipv[b] = piv.p + (size_t)b * maxn;
@@ -2026,7 +2063,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       return r;
     };
     struct Step {
-      size_t pd = 0, pp = 0, pn = 0, psrc = 0, pld = 0;
+      size_t pd = 0, pp = 0, pn = 0, psrc = 0, pld = 0, fix = 0;
       int npd = 0, hmax = 0, pmax = 0;
       CopyPrep cC, cRow;
       GemmPrep gR, gUpd, gCol;
@@ -2040,6 +2077,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       std::vector<int> pn, pld;
       std::vector<CopyDesc<T>> cC, cRow;
       std::vector<GemmDesc<T>> gR, gUpd, gCol;
+      std::vector<GjFix> fix;
       for (int b = 0; b < nbm; ++b) {
         const int n = bn[b];
         if (k0 >= n) continue;
@@ -2062,8 +2100,15 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
                         n - k0 - pb, 0, 0, T(1)});
         gR.push_back({n, pb, pb, 0, 0, A + (size_t)k0 * n, n, poff[b], pb, roff[b], n, T(1), T(0)});
         gUpd.push_back({n, n, pb, 0, 0, roff[b], n, coff[b], pb, A, n, T(-1), T(1)});
-        cRow.push_back({roff[b], n, A + (size_t)k0 * n, n, n, pb, 0, 0, T(1)});
-        gCol.push_back({pb, n, pb, 0, 0, poff[b], pb, coff[b], pb, A + k0, n, T(-1), T(0)});
+        if constexpr (fused) {
+          // -P C into its own buffer, in the same launch as R; the update's
+          // epilogue then writes R into columns p and -P C into rows p
+          gR.push_back({pb, n, pb, 0, 0, poff[b], pb, coff[b], pb, cpoff[b], pb, T(-1), T(0)});
+          fix.push_back({(const double *)roff[b], (const double *)cpoff[b], k0, pb});
+        } else {
+          cRow.push_back({roff[b], n, A + (size_t)k0 * n, n, n, pb, 0, 0, T(1)});
+          gCol.push_back({pb, n, pb, 0, 0, poff[b], pb, coff[b], pb, A + k0, n, T(-1), T(0)});
+        }
       }
       if (pd.empty()) break;
       Step st_;
@@ -2080,6 +2125,9 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       st_.gUpd = prep_gemm(gUpd);
       st_.cRow = prep_copy(cRow);
       st_.gCol = prep_gemm(gCol);
+      // the fused update's fixes follow gUpd's descriptors one to one (all
+      // of them have m, n > 0, so prep_gemm keeps every one)
+      st_.fix = add(fix.data(), fix.size() * sizeof(GjFix));
       steps.push_back(st_);
     }
     char *db = (char *)st.put(blob.data(), blob.size(), s);
@@ -2114,10 +2162,19 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         SBIE_LAUNCH_CHECK();
       }
       copy_step(q.cC);                                                  // C = A[p, :], C[:, p] = -I
-      gemm_step(q.gR);                                                  // R = A[:, p] P
-      gemm_step(q.gUpd);                                                // A -= R C
-      copy_step(q.cRow);                                                // A[:, p] = R
-      gemm_step(q.gCol);                                                // A[p, :] = -P C
+      gemm_step(q.gR);                                                  // R = A[:, p] P (and -P C)
+      if constexpr (fused) {                                            // A -= R C, A[:, p] = R, A[p, :] = -P C
+        if (q.gUpd.nt) {
+          gemm_tiles_mfma_gj<<<q.gUpd.nt, 256, 0, s>>>((const GemmDesc<double> *)(db + q.gUpd.d),
+                                                       (const int2 *)(db + q.gUpd.t),
+                                                       (const GjFix *)(db + q.fix));
+          SBIE_LAUNCH_CHECK();
+        }
+      } else {
+        gemm_step(q.gUpd);                                              // A -= R C
+        copy_step(q.cRow);                                              // A[:, p] = R
+        gemm_step(q.gCol);                                              // A[p, :] = -P C
+      }
     }
     unpermute_rows_kernel<T><<<dim3(ceil_div(maxn, kUnpermCols), nbm), 256, (size_t)maxn * sizeof(T), s>>>(
         mat_dev, n_dev, lab_dev);
