@@ -480,10 +480,88 @@ __global__ void scatter_sol(const int64_t *__restrict__ dofs, int64_t n, const T
 // ---------------------------------------------------------------------------
 // Factorisation state
 // ---------------------------------------------------------------------------
-struct PairHash {
-  size_t operator()(const std::pair<int, int> &p) const {
-    return std::hash<int64_t>()(((int64_t)p.first << 32) ^ (uint32_t)p.second);
+// Hash map from a pair of box indices to V: open addressing with linear
+// probing in one flat array (power-of-two capacity, at most half full), so
+// that the tens of thousands of blocks of a level cost no allocation each.
+// find() returns a pointer to the (key, value) pair or end() (null);
+// entries are never erased; emplace keeps an existing entry.  References
+// stay valid only until the next emplace.
+template <class V>
+class PairMap {
+ public:
+  using value_type = std::pair<std::pair<int, int>, V>;
+  void reserve(size_t n) {
+    if (2 * n > cap_) rehash(pow2(2 * n));
   }
+  value_type *find(const std::pair<int, int> &k) {
+    if (cap_ == 0) return nullptr;
+    for (size_t i = slot(k);; i = (i + 1) & (cap_ - 1)) {
+      if (!used_[i]) return nullptr;
+      if (tab_[i].first == k) return &tab_[i];
+    }
+  }
+  value_type *end() const { return nullptr; }
+  void emplace(const std::pair<int, int> &k, const V &v) {
+    if (2 * (n_ + 1) > cap_) rehash(pow2(std::max<size_t>(16, 2 * cap_)));
+    for (size_t i = slot(k);; i = (i + 1) & (cap_ - 1)) {
+      if (!used_[i]) {
+        used_[i] = 1;
+        tab_[i] = value_type(k, v);
+        ++n_;
+        return;
+      }
+      if (tab_[i].first == k) return;
+    }
+  }
+
+ private:
+  std::vector<value_type> tab_;
+  std::vector<unsigned char> used_;
+  size_t cap_ = 0, n_ = 0;
+  static size_t pow2(size_t n) {
+    size_t c = 16;
+    while (c < n) c <<= 1;
+    return c;
+  }
+  // the 64-bit finaliser of MurmurHash3 on the packed pair
+  size_t slot(const std::pair<int, int> &k) const {
+    uint64_t x = ((uint64_t)(uint32_t)k.first << 32) | (uint32_t)k.second;
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return (size_t)x & (cap_ - 1);
+  }
+  void rehash(size_t c) {
+    std::vector<value_type> old;
+    std::vector<unsigned char> oldu;
+    old.swap(tab_);
+    oldu.swap(used_);
+    tab_.assign(c, value_type());
+    used_.assign(c, 0);
+    cap_ = c;
+    n_ = 0;
+    for (size_t i = 0; i < old.size(); ++i)
+      if (oldu[i]) emplace(old[i].first, old[i].second);
+  }
+};
+
+// Map from a box index to V for the handful of neighbours of one box:
+// linear search in a small vector (operator[] inserts a value-initialised
+// entry when the key is missing, like std::map).
+template <class V>
+class SmallMap {
+ public:
+  V &operator[](int k) {
+    for (auto &e : v_)
+      if (e.first == k) return e.second;
+    v_.emplace_back(k, V{});
+    return v_.back().second;
+  }
+
+ private:
+  std::vector<std::pair<int, V>> v_;
 };
 
 template <class T>
@@ -844,7 +922,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   // per-level state containers
   std::vector<int> m(nleaf);
   for (int b = 0; b < nleaf; ++b) m[b] = (int)tr.leaf_dofs[b].size();
-  std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> S;  // near field of the level
+  PairMap<Blk<T>> S;  // near field of the level
   auto level_arena = std::make_unique<Arena>((size_t)256 << 20, &chunk_cache);
   // leaf near field
   {
@@ -1016,7 +1094,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
     clk.tick("initial_bases");
     // ---- projections and initial couplings
     std::vector<T *> Gh(nb), Hh(nb), g0(nb), h0(nb);
-    std::unordered_map<std::pair<int, int>, Blk<T>, PairHash> Tc;
+    PairMap<Blk<T>> Tc;
     {
       std::vector<GemmDesc<T>> gd;
       for (int b = 0; b < nb; ++b) {
@@ -1178,7 +1256,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       }
       gemm_batched<T>(gd, st, s);
       // E: M_ik = A_xx S_ik, G_ik = A_zx S_ik, B_ij = S_ji A_xy
-      std::vector<std::unordered_map<int, T *>> Mik(ne), Gik(ne), Bij(ne), Nji(ne);
+      std::vector<SmallMap<T *>> Mik(ne), Gik(ne), Bij(ne), Nji(ne);
       gd.clear();
       for (int e = 0; e < ne; ++e) {
         const int i = E[e];
