@@ -1208,6 +1208,12 @@ struct PanelDesc {
   int *lab;      // n entries: original column now at each position
   int n, k0, pb;
   int32_t *info;
+  // when set (register panel kernel only): after the interchanges the same
+  // workgroup inverts the pivot block into P (pb x pb, failure into *tinfo)
+  // and writes C = A[p, :] with -I in the panel's columns (pb x n, leading
+  // dimension pb)
+  T *P = nullptr, *C = nullptr;
+  int32_t *tinfo = nullptr;
 };
 
 template <class T>
@@ -1336,6 +1342,92 @@ __device__ __forceinline__ void pin_registers(T (&v)[32]) {
   asm volatile("" : "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]), "+v"(v[20]), "+v"(v[21]),
                "+v"(v[22]), "+v"(v[23]), "+v"(v[24]), "+v"(v[25]), "+v"(v[26]), "+v"(v[27]), "+v"(v[28]),
                "+v"(v[29]), "+v"(v[30]), "+v"(v[31]));
+}
+
+// Gauss-Jordan inverse without interchanges, one wave per matrix of order
+// n <= NMAX, read from srcs[b] (leading dimension lds[b]) and written to
+// ptrs[b] (leading dimension n).  For the pivot blocks of the blocked
+// inverse: their columns were chosen by partial pivoting over the whole
+// panel, so the diagonal already holds the pivots an interchanging
+// elimination of the transposed block would take (the pivots of an
+// elimination without interchanges are ratios of leading principal minors,
+// the same for a matrix and its transpose).  Lane i keeps row i of
+// diag(M, I) (order NMAX) in registers; every lane reads the pivot row from
+// the pivot lane (readlane into scalar registers, no LDS round trip) and
+// scales it itself.  The steps run in a loop of U expanded steps, after
+// which the register columns rotate by U (NMAX steps rotate them back into
+// place): the code stays small enough for the instruction cache.
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int l);
+template <>
+__device__ __forceinline__ double lane_value<double>(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <>
+__device__ __forceinline__ float lane_value<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// One wave (lane i) inverts the matrix of order n <= NMAX at src (leading
+// dimension ld) into A (leading dimension n); a failure sets *info.
+template <class T, int NMAX>
+__device__ __forceinline__ void gj_nopiv_wave(const T *__restrict__ src, int ld, int n, T *__restrict__ A,
+                                              int32_t *__restrict__ info, int i) {
+  constexpr int U = 8;
+  static_assert(NMAX % U == 0 && NMAX <= 64, "the order is a multiple of the expanded steps");
+  T r[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : (i == c ? T(1) : T(0));
+  int fail_at = 0;   // 1 + the first step with a zero or non-finite pivot
+  for (int k0 = 0; k0 < NMAX; k0 += U) {
+    static_for<0, U>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;   // register column of step k
+      const int k = k0 + j;
+      // pivot row k scaled by 1 / pivot, with 1 / pivot in column j
+      const T inv = T(1) / lane_value(r[j], k);
+      T pr[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) pr[c] = c == j ? inv : lane_value(r[c], k) * inv;
+      // the elimination runs on after a failure; its values are discarded
+      if (fail_at == 0 && !isfinite((double)inv)) fail_at = k + 1;
+      if (i == k) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) r[c] = pr[c];
+      } else {
+        const T f = r[j];
+        r[j] = T(0);
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, pr[c], r[c]);
+      }
+    });
+    T head[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) head[c] = r[c];
+#pragma unroll
+    for (int c = 0; c + U < NMAX; ++c) r[c] = r[c + U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) r[NMAX - U + c] = head[c];
+  }
+  if (fail_at) {
+    if (i == 0) *info = fail_at;
+    return;
+  }
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < n) A[i + (size_t)c * n] = r[c];
+  }
+}
+
+template <class T, int NMAX>
+__global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict__ ptrs,
+                                                           const int *__restrict__ ns,
+                                                           int32_t *__restrict__ info,
+                                                           const T *const *__restrict__ srcs,
+                                                           const int *__restrict__ lds) {
+  const int b = blockIdx.x;
+  gj_nopiv_wave<T, NMAX>(srcs[b], lds[b], ns[b], ptrs[b], info + b, threadIdx.x);
 }
 
 template <class T, int THREADS, int SLOTS>
@@ -1476,7 +1568,7 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
   }
   panel_sync<THREADS>();
   const int nu = s_nu, na = s_na;
-  if (nu == 0) return;
+  if (nu > 0) {
   {
     // the column labels follow the same permutation (all reads before the
     // barrier, all writes after it)
@@ -1498,6 +1590,19 @@ __global__ __launch_bounds__(THREADS) void panel_pivot_reg_kernel(const PanelDes
   __syncthreads();
   for (int i = 0; i < na; ++i)
     for (int r = tid; r < d.n; r += THREADS) d.A[r + (size_t)u_pos[i] * d.n] = d.work[r + (size_t)i * d.n];
+  }
+  if (d.P == nullptr) return;
+  __syncthreads();   // the interchanged columns are visible to every wave
+  if (wv == 0) {
+    gj_nopiv_wave<T, PB>(d.A + d.k0 + (size_t)d.k0 * d.n, d.n, pb, d.P, d.tinfo, lane);
+  } else {
+    for (int e = tid - 64; e < pb * d.n; e += THREADS - 64) {
+      const int j = e / pb, t = e - j * pb;
+      const T v = (j >= d.k0 && j < d.k0 + pb) ? (j - d.k0 == t ? T(-1) : T(0))
+                                               : d.A[(d.k0 + t) + (size_t)j * d.n];
+      d.C[t + (size_t)j * pb] = v;
+    }
+  }
 }
 
 template <class T>
@@ -1848,88 +1953,6 @@ __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs
     for (int c = 0; c < n; ++c) A[i + (size_t)c * n] = out[i][lab[c]];
 }
 
-// Gauss-Jordan inverse without interchanges, one wave per matrix of order
-// n <= NMAX, read from srcs[b] (leading dimension lds[b]) and written to
-// ptrs[b] (leading dimension n).  For the pivot blocks of the blocked
-// inverse: their columns were chosen by partial pivoting over the whole
-// panel, so the diagonal already holds the pivots an interchanging
-// elimination of the transposed block would take (the pivots of an
-// elimination without interchanges are ratios of leading principal minors,
-// the same for a matrix and its transpose).  Lane i keeps row i of
-// diag(M, I) (order NMAX) in registers; every lane reads the pivot row from
-// the pivot lane (readlane into scalar registers, no LDS round trip) and
-// scales it itself.  The steps run in a loop of U expanded steps, after
-// which the register columns rotate by U (NMAX steps rotate them back into
-// place): the code stays small enough for the instruction cache.
-template <class T>
-__device__ __forceinline__ T lane_value(T v, int l);
-template <>
-__device__ __forceinline__ double lane_value<double>(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-template <>
-__device__ __forceinline__ float lane_value<float>(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-template <class T, int NMAX>
-__global__ __launch_bounds__(64) void gj_nopiv_wave_kernel(T *const *__restrict__ ptrs,
-                                                           const int *__restrict__ ns,
-                                                           int32_t *__restrict__ info,
-                                                           const T *const *__restrict__ srcs,
-                                                           const int *__restrict__ lds) {
-  constexpr int U = 8;
-  static_assert(NMAX % U == 0 && NMAX <= 64, "the order is a multiple of the expanded steps");
-  const int b = blockIdx.x;
-  const int n = ns[b];
-  T *A = ptrs[b];
-  const T *src = srcs[b];
-  const int ld = lds[b];
-  const int i = threadIdx.x;
-  T r[NMAX];
-#pragma unroll
-  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : (i == c ? T(1) : T(0));
-  int fail_at = 0;   // 1 + the first step with a zero or non-finite pivot
-  for (int k0 = 0; k0 < NMAX; k0 += U) {
-    static_for<0, U>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;   // register column of step k
-      const int k = k0 + j;
-      // pivot row k scaled by 1 / pivot, with 1 / pivot in column j
-      const T inv = T(1) / lane_value(r[j], k);
-      T pr[NMAX];
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) pr[c] = c == j ? inv : lane_value(r[c], k) * inv;
-      // the elimination runs on after a failure; its values are discarded
-      if (fail_at == 0 && !isfinite((double)inv)) fail_at = k + 1;
-      if (i == k) {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) r[c] = pr[c];
-      } else {
-        const T f = r[j];
-        r[j] = T(0);
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, pr[c], r[c]);
-      }
-    });
-    T head[U];
-#pragma unroll
-    for (int c = 0; c < U; ++c) head[c] = r[c];
-#pragma unroll
-    for (int c = 0; c + U < NMAX; ++c) r[c] = r[c + U];
-#pragma unroll
-    for (int c = 0; c < U; ++c) r[NMAX - U + c] = head[c];
-  }
-  if (fail_at) {
-    if (i == 0) info[b] = fail_at;
-    return;
-  }
-  if (i < n) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      if (c < n) A[i + (size_t)c * n] = r[c];
-  }
-}
 
 template <class T>
 void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
@@ -2065,6 +2088,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
     struct Step {
       size_t pd = 0, pp = 0, pn = 0, psrc = 0, pld = 0, fix = 0;
       int npd = 0, hmax = 0, pmax = 0;
+      bool fused_panel = false;
       CopyPrep cC, cRow;
       GemmPrep gR, gUpd, gCol;
     };
@@ -2114,6 +2138,14 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       Step st_;
       st_.npd = (int)pd.size();
       for (const auto &q : pd) st_.hmax = std::max(st_.hmax, q.n - q.k0);
+      // the register panel kernel also inverts the pivot blocks and forms C
+      st_.fused_panel = st_.hmax <= kPanelRegRows;
+      if (st_.fused_panel)
+        for (size_t q = 0; q < pd.size(); ++q) {
+          pd[q].P = pp[q];
+          pd[q].C = coff[active[it][q]];
+          pd[q].tinfo = info_tile + (size_t)it * nbm + q;
+        }
       for (int q : pn) st_.pmax = std::max(st_.pmax, q);
       st_.pd = add(pd.data(), pd.size() * sizeof(PanelDesc<T>));
       st_.pp = add(pp.data(), pp.size() * sizeof(T *));
@@ -2151,7 +2183,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       else
         panel_pivot_kernel<T><<<(unsigned)q.npd, 256, 0, s>>>(dd);
       SBIE_LAUNCH_CHECK();
-      {                                                                 // P = A_pp^-1
+      if (!q.fused_panel) {                                             // P = A_pp^-1
         T *const *pp_ = (T *const *)(db + q.pp);
         const int *pn_ = (const int *)(db + q.pn);
         const T *const *ps_ = (const T *const *)(db + q.psrc);
@@ -2161,7 +2193,7 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
         gj_nopiv_wave_kernel<T, 32><<<(unsigned)q.npd, 64, 0, s>>>(pp_, pn_, inf, ps_, pl_);
         SBIE_LAUNCH_CHECK();
       }
-      copy_step(q.cC);                                                  // C = A[p, :], C[:, p] = -I
+      if (!q.fused_panel) copy_step(q.cC);                              // C = A[p, :], C[:, p] = -I
       gemm_step(q.gR);                                                  // R = A[:, p] P (and -P C)
       if constexpr (fused) {                                            // A -= R C, A[:, p] = R, A[p, :] = -P C
         if (q.gUpd.nt) {
