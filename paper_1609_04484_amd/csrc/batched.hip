@@ -1101,11 +1101,21 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
           }
         }
         __syncthreads();
-        for (int e = tid; e < ns * d.m; e += kPgsThreads) {
-          const int s = e / d.m, i = e - s * d.m;
-          double v = Q[e];
-          for (int col = cb; col < ce; ++col) v = fma(-d.W[i + (size_t)col * d.ldw], dots[col - cb][s], v);
-          Q[e] = v;
+        // a thread per row: each basis entry is loaded once for the whole
+        // block (same products and order per entry as one thread per entry)
+        for (int i = tid; i < d.m; i += kPgsThreads) {
+          double v[B];
+#pragma unroll
+          for (int s = 0; s < B; ++s) v[s] = s < ns ? Q[s * d.m + i] : 0.0;
+          for (int col = cb; col < ce; ++col) {
+            const double w = d.W[i + (size_t)col * d.ldw];
+#pragma unroll
+            for (int s = 0; s < B; ++s)
+              if (s < ns) v[s] = fma(-w, dots[col - cb][s], v[s]);
+          }
+#pragma unroll
+          for (int s = 0; s < B; ++s)
+            if (s < ns) Q[s * d.m + i] = v[s];
         }
         __syncthreads();
       }
