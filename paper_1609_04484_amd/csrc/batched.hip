@@ -860,6 +860,64 @@ __global__ __launch_bounds__(256) void gj_small_kernel(T *const *__restrict__ pt
 // In FP32 every accepted column is projected out of the candidates in place
 // (see pgs_kernel).  Reductions go through wave shuffles, then across the 16
 // waves in LDS.
+// Sums over the wave of B = 4 or 8 accumulators at once, each formed by the
+// same pairings as the halving tree (distances 32, 16, ..., 1; the sum of
+// two subtree values is exact under exchange, so the result equals the
+// shfl_down tree's in lane 0): at distances 32 and 16 (and 8 for B = 8)
+// every lane keeps half of its accumulators and receives the partner's
+// half of the same ones, the remaining distances are whole-wave exchanges.
+// Returns, in every lane, the total of accumulator wave_sums_slot<B>(lane).
+__device__ __forceinline__ void lane_swap32(double P, double Q, double &r0, double &r1) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(P), __double2loint(Q), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(P), __double2hiint(Q), false, false);
+  r0 = __hiloint2double(hi[0], lo[0]);   // lanes 32..63: Q of lane - 32
+  r1 = __hiloint2double(hi[1], lo[1]);   // lanes 0..31: P of lane + 32
+}
+__device__ __forceinline__ void lane_swap16(double P, double Q, double &r0, double &r1) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(P), __double2loint(Q), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(P), __double2hiint(Q), false, false);
+  r0 = __hiloint2double(hi[0], lo[0]);   // lanes with bit 16 set: Q of lane - 16
+  r1 = __hiloint2double(hi[1], lo[1]);   // lanes with bit 16 clear: P of lane + 16
+}
+template <int B>
+__device__ __forceinline__ int wave_sums_slot(int lane) {
+  return B == 8 ? ((lane >> 3) & 1) | ((lane >> 3) & 2) | ((lane >> 3) & 4) : ((lane >> 4) & 1) | ((lane >> 4) & 2);
+}
+template <int B>
+__device__ __forceinline__ int wave_sums_lane(int s) {
+  return B == 8 ? 8 * (s & 1) + 8 * (s & 2) + 8 * (s & 4) : 16 * (s & 1) + 16 * (s & 2);
+}
+template <int B>
+__device__ __forceinline__ double wave_sums(const double (&a)[B], int lane) {
+  static_assert(B == 4 || B == 8, "four or eight accumulators");
+  constexpr int H1 = B / 2, H2 = B / 4;
+  const bool hi32 = lane & 32, hi16 = lane & 16;
+  double b[H1], c[H2];
+#pragma unroll
+  for (int q = 0; q < H1; ++q) {
+    double r0, r1;
+    lane_swap32(a[q], a[H1 + q], r0, r1);
+    b[q] = hi32 ? a[H1 + q] + r0 : a[q] + r1;
+  }
+#pragma unroll
+  for (int q = 0; q < H2; ++q) {
+    double r0, r1;
+    lane_swap16(b[q], b[H2 + q], r0, r1);
+    c[q] = hi16 ? b[H2 + q] + r0 : b[q] + r1;
+  }
+  double d;
+  if constexpr (H2 == 2) {
+    const bool hi8 = lane & 8;
+    d = (hi8 ? c[1] : c[0]) + dpp_f64<0x128>(hi8 ? c[0] : c[1]);   // row_ror:8, lane ^ 8
+  } else {
+    d = c[0] + dpp_f64<0x128>(c[0]);
+  }
+  d += dpp_f64<0x1B>(dpp_f64<0x141>(d));   // lane ^ 4: half-row mirror, then quad_perm [3,2,1,0]
+  d += dpp_f64<0x4E>(d);                   // lane ^ 2
+  d += dpp_f64<0xB1>(d);                   // lane ^ 1
+  return d;
+}
+
 constexpr int kPgsThreads = 1024;
 constexpr int kPgsWaves = kPgsThreads / 64;
 
@@ -1093,12 +1151,8 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
             for (int s = 0; s < B; ++s)
               if (s < ns) acc[s] = fma(wi, Q[s * d.m + i], acc[s]);
           }
-#pragma unroll
-          for (int s = 0; s < B; ++s) {
-            double v = acc[s];
-            v = wave_sum_lane0(v);
-            if (lane == 0) dots[col - cb][s] = v;
-          }
+          const double v = wave_sums<B>(acc, lane);
+          if ((lane & (B == 8 ? 7 : 15)) == 0) dots[col - cb][wave_sums_slot<B>(lane)] = v;
         }
         __syncthreads();
         // a thread per row: each basis entry is loaded once for the whole
@@ -1183,11 +1237,11 @@ __global__ __launch_bounds__(kPgsThreads) void pgs_block_kernel(const PgsDesc<do
         for (int s = 0; s < B; ++s)
           if (s < na) acc[s] = fma(Q[s * d.m + i], ci, acc[s]);
       }
+      const double tot = wave_sums<B>(acc, lane);
       double dn = 0.0;
 #pragma unroll
       for (int s = 0; s < B; ++s) {
-        double v = acc[s];
-        v = wave_sum_lane0(v);
+        const double v = readlane_f64(tot, wave_sums_lane<B>(s));
         dn = fma(v, v, dn);
       }
       if (lane == 0) norms[j] -= dn;
