@@ -2,6 +2,7 @@
 #include <cstring>
 #include <exception>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <type_traits>
 
@@ -49,12 +50,18 @@ StagerLease::~StagerLease() {
   g_stager_pool[dev_].push_back(st_);
 }
 
+HostProf &host_prof() {
+  thread_local HostProf h;
+  return h;
+}
+
 OpFlops &op_flops() {
   thread_local OpFlops f;
   return f;
 }
 
 void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
+  HostScope hs(HostProf::kStage);
   const size_t need = (bytes + 255) & ~size_t(255);
   if (need > cap) fail(SBIE_OUT_OF_MEMORY, "descriptor batch of %zu bytes exceeds staging", bytes);
   if (used + need > cap) {
@@ -72,6 +79,7 @@ void *Stager::put(const void *src, size_t bytes, hipStream_t s) {
 
 void Stager::put_many(const std::vector<std::pair<const void *, size_t>> &parts, std::vector<void *> &dst,
                       hipStream_t s) {
+  HostScope hs(HostProf::kStage);
   size_t need = 0;
   for (const auto &p : parts) need += (p.second + 255) & ~size_t(255);
   if (need > cap) fail(SBIE_OUT_OF_MEMORY, "descriptor batch of %zu bytes exceeds staging", need);
@@ -428,6 +436,7 @@ __global__ __launch_bounds__(256) void gemm_tiles_mfma_lowin(const GemmDesc<T> *
 // with inputs rounded to FP16 or BF16 when the caller asks for it.
 template <class T>
 void launch_gemm_tiles(unsigned nt, const GemmDesc<T> *dd, const int2 *td, hipStream_t s, GemmInputs in) {
+  HostScope hs(HostProf::kLaunch);
   if (in == GemmInputs::kF16)
     gemm_tiles_mfma_lowin<T, GemmInputs::kF16><<<nt, 256, 0, s>>>(dd, td);
   else if (in == GemmInputs::kBF16)
@@ -1776,6 +1785,7 @@ __global__ void splitk_reduce(const T *__restrict__ part, int P, int m, int n, T
 
 template <class T>
 void gemm_batched_impl(const std::vector<GemmDesc<T>> &d, Stager &st, hipStream_t s, GemmInputs in) {
+  HostScope hs(HostProf::kGemm);
   OpFlops &fl = op_flops();
   for (const auto &g : d)
     if (g.m > 0 && g.n > 0 && g.k > 0) {
@@ -1898,6 +1908,7 @@ void copy_launch(const CopyDesc<T> *d, int nd, int max_cols, hipStream_t s) {
 
 template <class T>
 void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s) {
+  HostScope hs(HostProf::kCopy);
   std::vector<CopyDesc<T>> keep;
   int max_cols = 0;
   for (const auto &c : d)
@@ -2045,6 +2056,7 @@ void inverse_batched(const std::vector<T *> &ptrs, const std::vector<int> &ns,
 template <class T>
 void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int> &ns,
                              int32_t *info_dev, Stager &st, hipStream_t s) {
+  std::unique_ptr<HostScope> prep(new HostScope(HostProf::kInvPrep));
   const int nm = (int)ptrs.size();
   if (nm == 0) return;
   std::vector<T *> sp, bp;
@@ -2227,6 +2239,8 @@ void inverse_batched_blocked(const std::vector<T *> &ptrs, const std::vector<int
       steps.push_back(st_);
     }
     char *db = (char *)st.put(blob.data(), blob.size(), s);
+    prep.reset();
+    HostScope loop_scope(HostProf::kInvLaunch);
     auto copy_step = [&](const CopyPrep &c) {
       copy_launch<T>((const CopyDesc<T> *)(db + c.d), c.n, c.max_cols, s);
     };
@@ -2342,6 +2356,7 @@ void normalize_columns(T *A, int lda, int rows, int cols, hipStream_t s) {
 
 template <class T>
 void pgs_batched(const std::vector<PgsDesc<T>> &d, Stager &st, hipStream_t s) {
+  HostScope hs(HostProf::kOther);
   if (d.empty()) return;
   size_t shmem = 0;
   for (const auto &p : d) {

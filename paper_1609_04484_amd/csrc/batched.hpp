@@ -1,6 +1,7 @@
 // Variable-size batched dense kernels used by the IFMM factorisation and
 // solve, templated on the working precision (double or float).
 #pragma once
+#include <chrono>
 
 #include "common.hpp"
 
@@ -97,6 +98,25 @@ class StagerLease {
 // Algorithmic flop counts of the batched products and inverses issued by the
 // calling thread (GEMM 2 m n k; Gauss-Jordan inverse 2 n^3), the op log of
 // a factorisation.  Reset and read by its caller.
+// Host time spent in the batched operations' own code (set up, staging,
+// launches), per thread, for the factorisation's verbose report.
+struct HostProf {
+  enum Slot { kGemm, kStage, kLaunch, kCopy, kInvPrep, kInvLaunch, kOther, kAlloc, kSlots };
+  double t[kSlots] = {};
+  int64_t n[kSlots] = {};
+};
+HostProf &host_prof();
+struct HostScope {
+  int k;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostScope(int slot) : k(slot), t0(std::chrono::steady_clock::now()) {}
+  ~HostScope() {
+    HostProf &h = host_prof();
+    h.t[k] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ++h.n[k];
+  }
+};
+
 struct OpFlops {
   double gemm = 0.0, inverse = 0.0;
   double gemm_low = 0.0;   // the part of gemm run with FP16/BF16 inputs

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <ctime>
 #include <unordered_map>
 
 #include "assemble.hpp"
@@ -599,9 +600,28 @@ struct StageClock {
   bool on = false;
   hipStream_t s = nullptr;
   std::chrono::steady_clock::time_point last;
-  std::map<std::string, double> acc;
+  std::map<std::string, double> acc, host;   // wall time; time until the stage's last enqueue
+  std::map<std::string, double> waits;       // host time blocked in the stage's own read-backs
+  std::map<std::string, double> cpu;         // CPU time of the calling thread
+  double wait_now = 0.0, cpu_last = 0.0;
+  static double thread_cpu() {
+    timespec ts;
+    clock_gettime(CLOCK_THREAD_CPUTIME_ID, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+  }
+  // a read-back inside a stage: synchronise, counting the time blocked
+  void sync(hipStream_t st) {
+    if (!on) {
+      SBIE_HIP(hipStreamSynchronize(st));
+      return;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    SBIE_HIP(hipStreamSynchronize(st));
+    wait_now += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   explicit StageClock(hipStream_t st) : on(std::getenv("SBIE_VERBOSE") != nullptr), s(st) {
     last = std::chrono::steady_clock::now();
+    cpu_last = thread_cpu();
   }
   void tick(const char *name, int level = -1) {
     if (!on) return;
@@ -614,10 +634,17 @@ struct StageClock {
     tick_s(name);
   }
   void tick_s(const std::string &name) {
+    const auto enq = std::chrono::steady_clock::now();
+    const double c = thread_cpu();
+    cpu[name] += c - cpu_last;
     (void)hipStreamSynchronize(s);
     const auto now = std::chrono::steady_clock::now();
     acc[name] += std::chrono::duration<double>(now - last).count();
+    host[name] += std::chrono::duration<double>(enq - last).count();
+    waits[name] += wait_now;
+    wait_now = 0.0;
     last = now;
+    cpu_last = thread_cpu();
   }
   ~StageClock() {
     if (!on) return;
@@ -626,6 +653,22 @@ struct StageClock {
     std::fprintf(stderr, "[ifmm] factor stages (s):");
     for (auto &kv : acc) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
     std::fprintf(stderr, " total=%.4f\n", tot);
+    // a stage whose host part is close to its wall time waited for the host
+    std::fprintf(stderr, "[ifmm] host part of each stage (s):");
+    for (auto &kv : host) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
+    std::fprintf(stderr, "\n[ifmm] read-back waits inside each stage (s):");
+    for (auto &kv : waits) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
+    std::fprintf(stderr, "\n[ifmm] CPU time of the host thread until each stage's last enqueue (s):");
+    for (auto &kv : cpu) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
+    std::fprintf(stderr, "\n");
+    {
+      const HostProf &h = host_prof();
+      const char *nm[HostProf::kSlots] = {"gemm_batched", "staging", "gemm_launch", "copy_batched",
+                                          "inverse_prep", "inverse_launches", "gram_schmidt", "alloc"};
+      std::fprintf(stderr, "[ifmm] host time in batched operations since process start (s, calls):");
+      for (int k = 0; k < HostProf::kSlots; ++k) std::fprintf(stderr, " %s=%.4f/%lld", nm[k], h.t[k], (long long)h.n[k]);
+      std::fprintf(stderr, "\n");
+    }
   }
 };
 
@@ -893,7 +936,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
   wall_length(g, wl.p, s);
   double wall_len = 1.0;
   SBIE_HIP(hipMemcpyAsync(&wall_len, wl.p, 8, hipMemcpyDeviceToHost, s));
-  SBIE_HIP(hipStreamSynchronize(s));
+  clk.sync(s);
   if (!(wall_len > 0.0)) wall_len = 1.0;
   const GeomView gv = make_view(g, wl.p);
   DevBuf<int32_t> info(2 * 65536);
@@ -1019,7 +1062,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
                      norms.p, st, s);
     double hn[2];
     SBIE_HIP(hipMemcpyAsync(hn, norms.p, 16, hipMemcpyDeviceToHost, s));
-    SBIE_HIP(hipStreamSynchronize(s));
+    clk.sync(s);
     const int cap_u = std::min(2 * n2, ps), cap_v = std::min(7 * n2, ps);
     T *uk = phase_arena.get<T>((size_t)2 * n2 * cap_u);
     T *vk = phase_arena.get<T>((size_t)7 * n2 * cap_v);
@@ -1033,7 +1076,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
                    st, s);
     int hc[2];
     SBIE_HIP(hipMemcpyAsync(hc, counts.p, 8, hipMemcpyDeviceToHost, s));
-    SBIE_HIP(hipStreamSynchronize(s));
+    clk.sync(s);
     st.reset();
     const int ru = hc[0], rv = hc[1];
     // reduced M2L per offset: U_K^T K_o V_K
@@ -1087,7 +1130,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       pgs_batched<T>(pd, st, s);
       std::vector<int> hr(nb);
       SBIE_HIP(hipMemcpyAsync(hr.data(), counts.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-      SBIE_HIP(hipStreamSynchronize(s));
+      clk.sync(s);
       st.reset();
       r = hr;
     }
@@ -1166,7 +1209,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       for (size_t q = 0; q < gd2.size(); ++q) (q % 2 ? gb2 : ga).push_back(gd2[q]);
       gemm_batched<T>(ga, st, s);
       gemm_batched<T>(gb2, st, s);
-      SBIE_HIP(hipStreamSynchronize(s));
+      clk.sync(s);
       st.reset();
     }
 
@@ -1322,7 +1365,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         SBIE_HIP(hipMemcpyAsync(hnorm.data(), norms.p, nd.size() * 8, hipMemcpyDeviceToHost, s));
       std::vector<int32_t> hinfo(2 * ne);
       SBIE_HIP(hipMemcpyAsync(hinfo.data(), info.p, 2 * ne * 4, hipMemcpyDeviceToHost, s));
-      SBIE_HIP(hipStreamSynchronize(s));
+      clk.sync(s);
       st.reset();
       for (int e = 0; e < ne; ++e)
         if (hinfo[e] != 0) fail(SBIE_BREAKDOWN, "singular near-field pivot at level %d", lev);
@@ -1346,11 +1389,15 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       {
         size_t q = 0;
         std::unordered_map<int, int> slot;
+        // the fill-ins of each eliminated box are contiguous in `far`
+        std::vector<size_t> far_end(ne + 1, 0);
+        for (const Far &f : far) ++far_end[f.e + 1];
+        for (int e = 0; e < ne; ++e) far_end[e + 1] += far_end[e];
         for (int e = 0; e < ne; ++e)
           for (int j : act[e]) {
             int cols = 2 * r[E[e]];
-            for (auto &f : far)
-              if (f.e == e && (f.j == j || f.k == j)) cols += kSketch;
+            for (size_t fi = far_end[e]; fi < far_end[e + 1]; ++fi)
+              if (far[fi].j == j || far[fi].k == j) cols += kSketch;
             slot[j] = (int)aug.size();
             aug.push_back({j, e, pa.get<T>((size_t)m[j] * std::max(1, cols)), cols});
           }
@@ -1456,7 +1503,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       pgs_batched<T>(pd, st, s);
       std::vector<int> add(aug.size() + 1, 0);
       SBIE_HIP(hipMemcpyAsync(add.data(), counts.p, (aug.size() + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-      SBIE_HIP(hipStreamSynchronize(s));
+      clk.sync(s);
       st.reset();
       std::vector<int> rold = r;
       for (size_t a = 0; a < aug.size(); ++a) r[aug[a].j] += add[a];
@@ -1622,7 +1669,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
         plist.push_back(ph);
       }
     }
-    SBIE_HIP(hipStreamSynchronize(s));
+    clk.sync(s);
     st.reset();
     // advance
     clk.tick("solve_plan");
@@ -1656,7 +1703,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       inverse_batched_blocked<T>({root_inv}, {root_dim}, info.p, st, s);
       int32_t hi = 0;
       SBIE_HIP(hipMemcpyAsync(&hi, info.p, 4, hipMemcpyDeviceToHost, s));
-      SBIE_HIP(hipStreamSynchronize(s));
+      clk.sync(s);
       if (hi != 0) fail(SBIE_BREAKDOWN, "singular root system");
       std::vector<GemvDesc<T>> rdsc;
       std::vector<GemvTerm<T>> rt;
@@ -1667,7 +1714,7 @@ void IfmmImpl<T>::factor(const sbie_geom *g, const ifmm_params *prm, hipStream_t
       if (apply32) host_root = {rdsc, {}, rt, {}};
     }
   }
-  SBIE_HIP(hipStreamSynchronize(s));
+  clk.sync(s);
   clk.tick("root");
   level_arena.reset();
   plan.rhs0 = rhs[0];
