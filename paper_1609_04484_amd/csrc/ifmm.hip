@@ -601,7 +601,10 @@ struct StageClock {
   hipStream_t s = nullptr;
   std::chrono::steady_clock::time_point last;
   std::map<std::string, double> acc, host;   // wall time; time until the stage's last enqueue
-  std::map<std::string, double> waits;       // host time blocked in the stage's own read-backs
+  // host time blocked in the stage's own synchronisations; a read-back into
+  // pageable memory already blocks inside the copy, so this is a lower bound
+  // of the time the host waited for the device
+  std::map<std::string, double> waits;
   std::map<std::string, double> cpu;         // CPU time of the calling thread
   double wait_now = 0.0, cpu_last = 0.0;
   static double thread_cpu() {
@@ -653,7 +656,7 @@ struct StageClock {
     std::fprintf(stderr, "[ifmm] factor stages (s):");
     for (auto &kv : acc) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
     std::fprintf(stderr, " total=%.4f\n", tot);
-    // a stage whose host part is close to its wall time waited for the host
+    // the host part runs until the stage's last enqueue (read-backs included)
     std::fprintf(stderr, "[ifmm] host part of each stage (s):");
     for (auto &kv : host) std::fprintf(stderr, " %s=%.4f", kv.first.c_str(), kv.second);
     std::fprintf(stderr, "\n[ifmm] read-back waits inside each stage (s):");
