@@ -1925,17 +1925,23 @@ void copy_batched(const std::vector<CopyDesc<T>> &d, Stager &st, hipStream_t s) 
 }
 
 // Gauss-Jordan inverse with partial pivoting of one matrix of order n <=
-// NMAX per wave (64 threads), in place: lane i keeps row i in registers, the
-// column loop is expanded at compile time, so no step needs a barrier.  The
-// pivot is a shuffle argmax; rows k and p trade places and the scaled pivot
-// row is broadcast through LDS.  Same operations as gj_small_kernel; the
-// column interchanges are undone through LDS on the way out.
+// NMAX per wave (64 threads), in place: lane i keeps row i of diag(M, I)
+// (order NMAX) in registers, so no step needs a barrier.  The pivot is the
+// largest |entry| of the column (lowest row on ties), by DPP exchanges; rows
+// k and p trade places through LDS; every lane reads the pivot row from the
+// pivot lane (readlane) and scales it itself.  The steps run in a loop of
+// eight expanded steps, after which the register columns rotate by eight
+// (NMAX steps rotate them back), so that the code fits the instruction
+// cache.  Same operations as gj_small_kernel; the column interchanges are
+// undone through LDS on the way out.
 template <class T, int NMAX>
 __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs, const int *__restrict__ ns,
                                                      int32_t *__restrict__ info,
                                                      const T *const *__restrict__ srcs = nullptr,
                                                      const int *__restrict__ lds = nullptr) {
-  __shared__ T xk[NMAX], xp[NMAX], prow[NMAX];
+  constexpr int U = 8;
+  static_assert(NMAX % U == 0 && NMAX <= 64, "the order is a multiple of the expanded steps");
+  __shared__ T xk[NMAX], xp[NMAX];
   __shared__ T out[NMAX][NMAX + 1];
   __shared__ int ipv[NMAX], lab[NMAX];
   const int b = blockIdx.x;
@@ -1948,66 +1954,67 @@ __global__ __launch_bounds__(64) void gj_wave_kernel(T *const *__restrict__ ptrs
   const int i = threadIdx.x;
   T r[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : T(0);
-  bool failed = false;
-  static_for<0, NMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (failed || k >= n) return;
-    double v = (i >= k && i < n) ? fabs((double)r[k]) : -1.0;
-    int bi = i;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(v, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
-    }
-    const int p = __builtin_amdgcn_readfirstlane(bi);
-    if (!(v > 0.0) || !isfinite(v)) {
-      if (i == 0) info[b] = k + 1;
-      failed = true;
-      return;
-    }
-    if (i == 0) ipv[k] = p;
-    if (p != k) {
+  for (int c = 0; c < NMAX; ++c) r[c] = (i < n && c < n) ? src[i + (size_t)c * ld] : (i == c ? T(1) : T(0));
+  int fail_at = 0;   // 1 + the first step without a positive finite pivot
+  for (int k0 = 0; k0 < NMAX; k0 += U) {
+    static_for<0, U>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;   // register column of step k
+      const int k = k0 + j;
+      double v = (i >= k && i < NMAX) ? fabs((double)r[j]) : -1.0;
+      if (!(v == v)) v = -1.0;                 // a NaN is no candidate
+      const double vmax = wave_max_f64(v);
+      const int p = wave_min_i32(v == vmax ? i : 0x7fffffff);
+      if (fail_at == 0 && (!(vmax > 0.0) || !isfinite(vmax))) fail_at = k + 1;
+      if (i == 0) ipv[k] = p < NMAX ? p : k;
+      if (p != k && p < NMAX) {
+        if (i == k) {
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) xk[c] = r[c];
+        }
+        if (i == p) {
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) xp[c] = r[c];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the rows are in LDS
+        __builtin_amdgcn_wave_barrier();
+        if (i == k) {
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) r[c] = xp[c];
+        }
+        if (i == p) {
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) r[c] = xk[c];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+      }
+      // pivot row k scaled by 1 / pivot, with 1 / pivot in column j
+      const T inv = T(1) / lane_value(r[j], k);
+      T pr[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) pr[c] = c == j ? inv : lane_value(r[c], k) * inv;
       if (i == k) {
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) xk[c] = r[c];
-      }
-      if (i == p) {
+        for (int c = 0; c < NMAX; ++c) r[c] = pr[c];
+      } else {
+        const T f = r[j];
+        r[j] = T(0);
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) xp[c] = r[c];
+        for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, pr[c], r[c]);
       }
-      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the rows are in LDS
-      __builtin_amdgcn_wave_barrier();
-      if (i == k) {
+    });
+    T head[U];
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) r[c] = xp[c];
-      }
-      if (i == p) {
+    for (int c = 0; c < U; ++c) head[c] = r[c];
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) r[c] = xk[c];
-      }
-    }
-    // scaled pivot row: row k with M[k][k] replaced by 1, divided by the pivot
-    if (i == k) {
-      const T inv = T(1) / r[k];
-      r[k] = T(1);
+    for (int c = 0; c + U < NMAX; ++c) r[c] = r[c + U];
 #pragma unroll
-      for (int c = 0; c < NMAX; ++c) {
-        r[c] *= inv;
-        prow[c] = r[c];
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
-    if (i != k && i < n) {
-      const T f = r[k];
-      r[k] = T(0);
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) r[c] = fma(-f, prow[c], r[c]);
-    }
-    __builtin_amdgcn_wave_barrier();
-  });
-  if (failed) return;
+    for (int c = 0; c < U; ++c) r[NMAX - U + c] = head[c];
+  }
+  if (fail_at) {
+    if (i == 0) info[b] = fail_at;
+    return;
+  }
   // column interchanges in reverse order, as one permutation of labels
   if (i == 0) {
     for (int c = 0; c < n; ++c) lab[c] = c;
